@@ -1,0 +1,142 @@
+"""ctypes declarations of the C ABI in include/dqaoa.h (argument marshalling
+only: every step of the state-vector path runs in the HIP library)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO = os.path.join(HERE, "libdqaoa.so")
+
+QAOA_C128 = 0
+QAOA_C64 = 1
+QAOA_MAX_N = 34
+QAOA_MAX_P = 64
+QAOA_DEVICE_NONE = -1
+
+OK = 0
+PENDING = 1
+ERR_INVALID_ARG = -1
+ERR_NO_DEVICE = -2
+ERR_OUT_OF_MEMORY = -3
+ERR_UNSUPPORTED = -4
+ERR_HIP = -5
+ERR_QUEUE_FULL = -6
+ERR_CANCELLED = -7
+ERR_TIMEOUT = -8
+ERR_NOT_FOUND = -9
+
+ERROR_NAMES = {
+    ERR_INVALID_ARG: "QAOA_ERR_INVALID_ARG", ERR_NO_DEVICE: "QAOA_ERR_NO_DEVICE",
+    ERR_OUT_OF_MEMORY: "QAOA_ERR_OUT_OF_MEMORY", ERR_UNSUPPORTED: "QAOA_ERR_UNSUPPORTED",
+    ERR_HIP: "QAOA_ERR_HIP", ERR_QUEUE_FULL: "QAOA_ERR_QUEUE_FULL",
+    ERR_CANCELLED: "QAOA_ERR_CANCELLED", ERR_TIMEOUT: "QAOA_ERR_TIMEOUT",
+    ERR_NOT_FOUND: "QAOA_ERR_NOT_FOUND",
+}
+
+# Every symbol include/dqaoa.h declares.
+EXPORTS = [
+    "qaoa_last_error", "qaoa_version", "qaoa_create", "qaoa_destroy",
+    "qaoa_expect", "qaoa_state", "qaoa_sample", "qaoa_grad", "qaoa_plan", "qaoa_plan_passes",
+    "qaoa_profile_enable", "qaoa_profile_read", "qaoa_queue_create",
+    "qaoa_queue_destroy", "qaoa_submit", "qaoa_poll", "qaoa_wait",
+    "qaoa_cancel", "qaoa_queue_get_stats",
+]
+
+
+class QaoaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("sets", ctypes.c_int), ("passes", ctypes.c_int),
+                ("state_reads", ctypes.c_int), ("state_writes", ctypes.c_int),
+                ("tile_qubits", ctypes.c_int), ("chunk_qubits", ctypes.c_int),
+                ("scratch_bytes", ctypes.c_size_t)]
+
+
+class QueueOpts(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int), ("max_pending", ctypes.c_int),
+                ("hbm_budget", ctypes.c_size_t), ("prec", ctypes.c_int),
+                ("p", ctypes.c_int), ("evals", ctypes.c_int),
+                ("shots", ctypes.c_int), ("lr", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double), ("batched", ctypes.c_int)]
+
+
+class SolveReq(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("Q", ctypes.POINTER(ctypes.c_double)),
+                ("gamma0", ctypes.POINTER(ctypes.c_double)),
+                ("beta0", ctypes.POINTER(ctypes.c_double)),
+                ("seed", ctypes.c_uint64)]
+
+
+class SolveResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("n", ctypes.c_int),
+                ("gamma", ctypes.c_double * QAOA_MAX_P),
+                ("beta", ctypes.c_double * QAOA_MAX_P),
+                ("expect", ctypes.c_double), ("best_z", ctypes.c_uint64),
+                ("best_c", ctypes.c_double), ("t_submit_ns", ctypes.c_int64),
+                ("t_admit_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64)]
+
+
+class QueueStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_longlong), ("admitted", ctypes.c_longlong),
+                ("completed", ctypes.c_longlong), ("cancelled", ctypes.c_longlong),
+                ("rejected", ctypes.c_longlong), ("steps", ctypes.c_longlong),
+                ("pending", ctypes.c_int), ("active", ctypes.c_int),
+                ("bytes_in_use", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def load():
+    """Loads the in-tree libdqaoa.so; raises if it has not been built (there
+    is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(SO):
+        raise RuntimeError(
+            f"{SO} is missing: build the HIP library first "
+            "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(SO)
+    vp, i, u64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_size_t
+    dp = ctypes.c_void_p
+    L.qaoa_last_error.restype = ctypes.c_char_p
+    L.qaoa_version.restype = ctypes.c_char_p
+    L.qaoa_create.argtypes = [ctypes.POINTER(vp), i, sz]
+    L.qaoa_destroy.argtypes = [vp]
+    L.qaoa_expect.argtypes = [vp, i, i, i, i, i, dp, dp, dp, dp, dp, dp, vp]
+    L.qaoa_state.argtypes = [vp, i, i, i, i, i, dp, dp, dp, dp, dp, dp, vp]
+    L.qaoa_sample.argtypes = [vp, i, i, i, i, dp, dp, dp, i, u64, dp, dp, dp,
+                              dp, dp, vp]
+    L.qaoa_grad.argtypes = [vp, i, i, i, i, i, dp, dp, dp, dp, dp, dp, vp]
+    L.qaoa_plan.argtypes = [vp, i, i, i, i, i, i, ctypes.POINTER(PlanInfo)]
+    L.qaoa_plan_passes.argtypes = [vp, i, i, i, i, vp, i, ctypes.POINTER(i)]
+    L.qaoa_profile_enable.argtypes = [vp, i]
+    L.qaoa_profile_read.argtypes = [vp, i, ctypes.POINTER(ctypes.c_longlong),
+                                    ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]
+    L.qaoa_queue_create.argtypes = [vp, ctypes.POINTER(QueueOpts), ctypes.POINTER(vp)]
+    L.qaoa_queue_destroy.argtypes = [vp]
+    L.qaoa_submit.argtypes = [vp, ctypes.POINTER(SolveReq), ctypes.POINTER(u64)]
+    L.qaoa_poll.argtypes = [vp, u64, ctypes.POINTER(SolveResult), vp]
+    L.qaoa_wait.argtypes = [vp, u64, ctypes.c_int64, ctypes.POINTER(SolveResult), vp]
+    L.qaoa_cancel.argtypes = [vp, u64]
+    L.qaoa_queue_get_stats.argtypes = [vp, ctypes.POINTER(QueueStats)]
+    for name in EXPORTS:
+        if name not in ("qaoa_last_error", "qaoa_version"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(rc: int, allow=(OK,)) -> int:
+    if rc in allow:
+        return rc
+    msg = load().qaoa_last_error().decode(errors="replace")
+    raise QaoaError(rc, msg)

@@ -1,0 +1,228 @@
+"""Python binding of the gfx950 QAOA library: torch tensors in, torch tensors
+out, all work queued on the current torch stream through the C ABI.
+
+Conventions (arXiv 2506.10531, Sec. IV, Eq. (1)-(2)): bit i of z is qubit i;
+layer 1 acts first on |+>; the mixer is e^{+i beta sum X} (H_X = -sum X);
+C(z) = z^T Q z for any dense real Q.
+"""
+from __future__ import annotations
+
+import ctypes
+import threading
+
+import torch
+
+from . import _lib
+
+PREC = {"c128": _lib.QAOA_C128, "c64": _lib.QAOA_C64}
+
+
+def _prec(prec) -> int:
+    if isinstance(prec, str):
+        if prec not in PREC:
+            raise ValueError(f"prec must be one of {list(PREC)}")
+        return PREC[prec]
+    return int(prec)
+
+
+class Context:
+    """A library context on one GPU (scratch memory, HBM budget)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        L = _lib.load()
+        h = ctypes.c_void_p()
+        _lib.check(L.qaoa_create(ctypes.byref(h), int(device), int(hbm_budget)))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            _lib.load().qaoa_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- measurement aids --
+    def profile(self, enable: bool = True):
+        _lib.check(_lib.load().qaoa_profile_enable(self.h, int(enable)))
+
+    def profile_read(self, reset: bool = True):
+        n = ctypes.c_longlong()
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        _lib.check(_lib.load().qaoa_profile_read(self.h, int(reset), ctypes.byref(n),
+                                                 ctypes.byref(ms), ctypes.byref(by)))
+        return n.value, ms.value, by.value
+
+    def plan(self, prec, B, n, p, S=1, grad=False) -> dict:
+        info = _lib.PlanInfo()
+        _lib.check(_lib.load().qaoa_plan(self.h, _prec(prec), B, n, p, S, int(grad),
+                                         ctypes.byref(info)))
+        return {f: getattr(info, f) for f, _ in info._fields_}
+
+
+_ctx_lock = threading.Lock()
+_default = {}
+
+
+def default_context(device: int | None = None) -> Context:
+    if device is None:
+        device = torch.cuda.current_device()
+    with _ctx_lock:
+        if device not in _default:
+            _default[device] = Context(device)
+        return _default[device]
+
+
+def host_context() -> Context:
+    """A context that validates and plans but runs nothing (no GPU needed)."""
+    with _ctx_lock:
+        if "host" not in _default:
+            _default["host"] = Context(_lib.QAOA_DEVICE_NONE)
+        return _default["host"]
+
+
+def _dev(t: torch.Tensor, name: str, dtype=torch.float64) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on a GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    return t.contiguous()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _shape_qp(Q, gammas, betas):
+    """Q [B,n,n] or [n,n]; gammas/betas [B,S,p], [S,p] or [p]."""
+    if Q.dim() == 2:
+        Q = Q.unsqueeze(0)
+    B, n, n2 = Q.shape
+    if n != n2:
+        raise ValueError("Q must be square")
+    g, b = gammas, betas
+    if g.shape != b.shape:
+        raise ValueError("gammas and betas must have the same shape")
+    if g.dim() == 1:
+        g, b = g.view(1, 1, -1), b.view(1, 1, -1)
+    elif g.dim() == 2:
+        g, b = g.unsqueeze(0), b.unsqueeze(0)
+    if g.shape[0] != B:
+        raise ValueError("leading dimension of gammas must match Q's batch")
+    return Q, g, b, B, n, g.shape[1], g.shape[2]
+
+
+def expect(Q, gammas, betas, prec="c64", probs=False, norm=False, ctx=None):
+    """<C> [B, S] of the Eq. (2) states (optionally norms and |psi|^2)."""
+    Q = _dev(Q, "Q")
+    gammas = _dev(gammas, "gammas")
+    betas = _dev(betas, "betas")
+    Q, g, b, B, n, S, p = _shape_qp(Q, gammas, betas)
+    pc = _prec(prec)
+    ctx = ctx or default_context(Q.device.index)
+    dev = Q.device
+    e = torch.empty((B, S), dtype=torch.float64, device=dev)
+    nr = torch.empty((B, S), dtype=torch.float64, device=dev) if norm else None
+    P = None
+    if probs:
+        dt = torch.float64 if pc == _lib.QAOA_C128 else torch.float32
+        P = torch.empty((B, S, 1 << n), dtype=dt, device=dev)
+    _lib.check(_lib.load().qaoa_expect(ctx.h, pc, B, n, p, S, _ptr(Q), _ptr(g), _ptr(b),
+                                       _ptr(e), _ptr(nr), _ptr(P), _stream()))
+    out = [e]
+    if norm:
+        out.append(nr)
+    if probs:
+        out.append(P)
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def state(Q, gammas, betas, prec="c64", ctx=None):
+    """(psi [B, S, 2^n] complex128/complex64, <C> [B, S], norm [B, S])."""
+    Q = _dev(Q, "Q")
+    gammas = _dev(gammas, "gammas")
+    betas = _dev(betas, "betas")
+    Q, g, b, B, n, S, p = _shape_qp(Q, gammas, betas)
+    pc = _prec(prec)
+    ctx = ctx or default_context(Q.device.index)
+    dev = Q.device
+    dt = torch.complex128 if pc == _lib.QAOA_C128 else torch.complex64
+    psi = torch.empty((B, S, 1 << n), dtype=dt, device=dev)
+    e = torch.empty((B, S), dtype=torch.float64, device=dev)
+    nr = torch.empty((B, S), dtype=torch.float64, device=dev)
+    _lib.check(_lib.load().qaoa_state(ctx.h, pc, B, n, p, S, _ptr(Q), _ptr(g), _ptr(b),
+                                      _ptr(psi), _ptr(e), _ptr(nr), _stream()))
+    return psi, e, nr
+
+
+def sample(Q, gammas, betas, shots: int, seed: int, prec="c64", ctx=None):
+    """dict(z [B, shots] int64 view of uint64, cz, best_z [B], best_c [B],
+    expect [B]).  Problem b uses SplitMix64 counters b*shots + s."""
+    Q = _dev(Q, "Q")
+    gammas = _dev(gammas, "gammas")
+    betas = _dev(betas, "betas")
+    if Q.dim() == 2:
+        Q = Q.unsqueeze(0)
+    B, n, _ = Q.shape
+    g = gammas.view(B, -1)
+    b = betas.view(B, -1)
+    p = g.shape[1]
+    ctx = ctx or default_context(Q.device.index)
+    dev = Q.device
+    z = torch.empty((B, shots), dtype=torch.int64, device=dev)
+    cz = torch.empty((B, shots), dtype=torch.float64, device=dev)
+    bz = torch.empty((B,), dtype=torch.int64, device=dev)
+    bc = torch.empty((B,), dtype=torch.float64, device=dev)
+    e = torch.empty((B,), dtype=torch.float64, device=dev)
+    _lib.check(_lib.load().qaoa_sample(ctx.h, _prec(prec), B, n, p, _ptr(Q), _ptr(g), _ptr(b),
+                                       int(shots), int(seed) & (2**64 - 1), _ptr(z), _ptr(cz),
+                                       _ptr(bz), _ptr(bc), _ptr(e), _stream()))
+    return dict(z=z, cz=cz, best_z=bz, best_c=bc, expect=e)
+
+
+def grad(Q, gammas, betas, prec="c64", ctx=None):
+    """(<C> [B,S], d<C>/dgamma [B,S,p], d<C>/dbeta [B,S,p]) by the adjoint
+    method."""
+    Q = _dev(Q, "Q")
+    gammas = _dev(gammas, "gammas")
+    betas = _dev(betas, "betas")
+    Q, g, b, B, n, S, p = _shape_qp(Q, gammas, betas)
+    ctx = ctx or default_context(Q.device.index)
+    dev = Q.device
+    e = torch.empty((B, S), dtype=torch.float64, device=dev)
+    dg = torch.empty((B, S, p), dtype=torch.float64, device=dev)
+    db = torch.empty((B, S, p), dtype=torch.float64, device=dev)
+    _lib.check(_lib.load().qaoa_grad(ctx.h, _prec(prec), B, n, p, S, _ptr(Q), _ptr(g),
+                                     _ptr(b), _ptr(e), _ptr(dg), _ptr(db), _stream()))
+    return e, dg, db
+
+
+class QAOAExpect(torch.autograd.Function):
+    """<C>(gamma, beta) with the adjoint-kernel gradient.
+
+    forward(Q [B,n,n], gammas [B,S,p], betas [B,S,p], prec) -> <C> [B,S];
+    backward scales d<C>/dgamma and d<C>/dbeta by grad_output."""
+
+    @staticmethod
+    def forward(ctx, Q, gammas, betas, prec="c64"):
+        e, dg, db = grad(Q.detach(), gammas.detach(), betas.detach(), prec=prec)
+        ctx.save_for_backward(dg, db)
+        ctx.gshape = gammas.shape
+        return e.view(gammas.shape[:-1])
+
+    @staticmethod
+    def backward(ctx, go):
+        dg, db = ctx.saved_tensors
+        go = go.reshape(dg.shape[:-1]).unsqueeze(-1)
+        return None, (dg * go).view(ctx.gshape), (db * go).view(ctx.gshape), None

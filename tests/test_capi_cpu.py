@@ -1,0 +1,146 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, validates arguments before any device work, and plans the
+state passes."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2506_10531_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dqaoa.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qaoa_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_what_binding_lists():
+    assert declared_functions() == sorted(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.load()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert L.qaoa_version().startswith(b"dqaoa")
+
+
+@pytest.fixture(scope="module")
+def hctx():
+    L = _lib.load()
+    h = ctypes.c_void_p()
+    assert L.qaoa_create(ctypes.byref(h), _lib.QAOA_DEVICE_NONE, 0) == _lib.OK
+    yield h
+    assert L.qaoa_destroy(h) == _lib.OK
+
+
+def _expect(h, prec=1, B=1, n=10, p=2, S=1, Q=1, g=1, b=1, e=1):
+    L = _lib.load()
+    P = lambda x: ctypes.c_void_p(0x1000) if x else None  # never dereferenced
+    return L.qaoa_expect(h, prec, B, n, p, S, P(Q), P(g), P(b), P(e), None, None, None)
+
+
+def test_valid_call_on_host_context_reports_no_device(hctx):
+    assert _expect(hctx) == _lib.ERR_NO_DEVICE
+    assert b"host-only" in _lib.load().qaoa_last_error()
+
+
+@pytest.mark.parametrize("kw", [
+    dict(prec=2), dict(prec=-1), dict(B=0), dict(S=0), dict(n=0), dict(n=35),
+    dict(p=0), dict(p=65), dict(Q=0), dict(g=0), dict(b=0), dict(e=0),
+    dict(B=300, S=300),
+])
+def test_invalid_arguments_rejected_before_device_work(hctx, kw):
+    assert _expect(hctx, **kw) == _lib.ERR_INVALID_ARG
+    assert _lib.load().qaoa_last_error() != b""
+
+
+def test_null_context_rejected():
+    assert _expect(None) == _lib.ERR_INVALID_ARG
+
+
+def test_budget_overrun_is_out_of_memory():
+    L = _lib.load()
+    h = ctypes.c_void_p()
+    assert L.qaoa_create(ctypes.byref(h), _lib.QAOA_DEVICE_NONE, 1 << 20) == _lib.OK
+    try:
+        # 2^24 complex64 amplitudes = 128 MiB of state: beyond a 1 MiB budget
+        assert _expect(h, n=24) == _lib.ERR_OUT_OF_MEMORY
+        # a single-tile state needs no state buffer: fits
+        assert _expect(h, n=12) == _lib.ERR_NO_DEVICE
+    finally:
+        L.qaoa_destroy(h)
+
+
+def test_sample_and_grad_validate(hctx):
+    L = _lib.load()
+    P = ctypes.c_void_p(0x1000)
+    rc = L.qaoa_sample(hctx, 1, 1, 10, 2, P, P, P, 0, 0, P, None, P, P, None, None)
+    assert rc == _lib.ERR_INVALID_ARG  # shots < 1
+    rc = L.qaoa_sample(hctx, 1, 1, 10, 2, P, P, P, 16, 0, P, None, P, P, None, None)
+    assert rc == _lib.ERR_NO_DEVICE
+    rc = L.qaoa_grad(hctx, 1, 1, 10, 2, 1, P, P, P, None, None, P, None)
+    assert rc == _lib.ERR_INVALID_ARG  # dgamma NULL
+    rc = L.qaoa_grad(hctx, 1, 1, 10, 2, 1, P, P, P, None, P, P, None)
+    assert rc == _lib.ERR_NO_DEVICE
+
+
+def test_no_gpu_create_reports_no_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    L = _lib.load()
+    h = ctypes.c_void_p()
+    assert L.qaoa_create(ctypes.byref(h), 0, 0) == _lib.ERR_NO_DEVICE
+
+
+def _plan(h, prec, n, p, grad=0, B=1, S=1):
+    info = _lib.PlanInfo()
+    assert _lib.load().qaoa_plan(h, prec, B, n, p, S, grad, ctypes.byref(info)) == 0
+    return info
+
+
+def test_plan_two_sets_reach_the_algorithmic_floor(hctx):
+    # n = 24 complex64 (14-qubit tiles, 4 contiguous low qubits): two qubit
+    # sets, p + 1 passes, one read and one write of the state per layer.
+    for p in (1, 2, 4, 6):
+        info = _plan(hctx, 1, 24, p)
+        assert (info.sets, info.passes) == (2, p + 1)
+        assert (info.state_reads, info.state_writes) == (p, p)
+        assert info.tile_qubits == 14 and info.chunk_qubits == 4
+
+
+def test_plan_single_tile_and_three_sets(hctx):
+    info = _plan(hctx, 1, 14, 3)
+    assert (info.sets, info.passes, info.state_reads) == (1, 1, 0)
+    info = _plan(hctx, 0, 13, 3)
+    assert (info.sets, info.passes) == (1, 1)
+    info = _plan(hctx, 1, 32, 2)
+    assert info.sets == 3 and info.passes == 1 + 2 * 2
+    # complex128 n = 24 fits two sets with 2 contiguous qubits (64-byte runs)
+    info = _plan(hctx, 0, 24, 4)
+    assert info.sets == 2 and info.chunk_qubits == 2
+
+
+def test_plan_scratch_accounts_for_checkpoints(hctx):
+    fwd = _plan(hctx, 1, 16, 6, grad=0, B=8)
+    grd = _plan(hctx, 1, 16, 6, grad=1, B=8)
+    state = 8 * (1 << 16) * 8
+    assert fwd.scratch_bytes >= state
+    # p + 1 passes: p checkpoints plus the adjoint state
+    assert grd.scratch_bytes >= (6 + 1) * state
+
+
+def test_package_imports_without_gpu():
+    import paper_2506_10531_amd as pkg
+    from paper_2506_10531_amd import api
+    assert pkg.expect is api.expect and pkg.grad is api.grad
+    assert pkg.workloads.qubo(3, 0).shape == (3, 3)
+    h = api.host_context()
+    info = h.plan("c64", 1, 24, 4)
+    assert info["passes"] == 5

@@ -1,0 +1,130 @@
+"""GPU parity of the HIP path against the CPU oracle (called through the C ABI
+by the Python binding).
+
+Tolerances (FP64 accumulation everywhere; state arithmetic in the precision
+named):
+  complex128: |d<C>| <= 1e-10 * max(|<C>|, 1); state L2 error <= 1e-12.
+  complex64:  |d<C>| <= 1e-5 * max_z |C(z)|; state L2 error <= 1e-4.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_10531_amd import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_E = {"c128": lambda e, cmax: 1e-10 * max(abs(e), 1.0),
+         "c64": lambda e, cmax: 1e-5 * cmax}
+TOL_PSI = {"c128": 1e-12, "c64": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def api():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2506_10531_amd import api as a
+    return a
+
+
+def cuda(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda:0")
+
+
+def cmax(Q):
+    return float(np.max(np.abs(oracle.cost_table(Q))))
+
+
+def run_case(api, n, p, S, prec, B=1, seed=0, state=True, probs=False):
+    Qs = workloads.qubos(B, n, 1000 + 7 * n + seed)
+    g, b = workloads.params(S, p, 2000 + n + seed, lead=(B,))
+    print(f"case n={n} p={p} S={S} B={B} prec={prec}", flush=True)
+    if state:
+        psi, e, nr = api.state(cuda(Qs), cuda(g), cuda(b), prec=prec)
+        psi = psi.cpu().numpy()
+    else:
+        e = api.expect(cuda(Qs), cuda(g), cuda(b), prec=prec)
+    e = e.cpu().numpy()
+    for bi in range(B):
+        cm = cmax(Qs[bi])
+        eo, no, Po = oracle.expect(Qs[bi], g[bi], b[bi], probs=probs)
+        for s in range(S):
+            err = abs(e[bi, s] - eo[s])
+            assert err <= TOL_E[prec](eo[s], cm), (bi, s, e[bi, s], eo[s], err)
+            if state:
+                ref = oracle.state(Qs[bi], g[bi, s], b[bi, s])
+                l2 = np.linalg.norm(psi[bi, s].astype(np.complex128) - ref)
+                assert l2 <= TOL_PSI[prec], (bi, s, l2)
+                assert abs(nr[bi, s].item() - 1.0) <= (1e-12 if prec == "c128" else 1e-5)
+    return Qs, g, b
+
+
+SMALL = [(n, p) for n in (1, 2, 3, 5, 8, 10, 12) for p in (1, 2, 3)]
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("n,p", SMALL)
+def test_single_tile_state_and_expect(api, n, p, prec):
+    run_case(api, n, p, S=3, prec=prec, B=2)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("n,p", [(13, 2), (14, 3), (15, 1), (16, 2), (17, 4), (19, 3),
+                                 (21, 2)])
+def test_multipass_state_and_expect(api, n, p, prec):
+    run_case(api, n, p, S=2, prec=prec, B=2 if n < 20 else 1)
+
+
+def test_plain_n10_all_sets_with_probabilities(api):
+    """64 parameter sets, p = 2, complex128, <C> and probabilities."""
+    W = workloads.WORKLOADS["plain_n10"]
+    Q = workloads.qubo(W["n"], W["q_seed"])
+    g, b = workloads.params(W["sets"], W["p"], W["p_seed"])
+    e, nr, P = api.expect(cuda(Q), cuda(g), cuda(b), prec="c128", probs=True, norm=True)
+    eo, no, Po = oracle.expect(Q, g, b, probs=True)
+    e = e.cpu().numpy()[0]
+    P = P.cpu().numpy()[0]
+    assert np.max(np.abs(e - eo) / np.maximum(np.abs(eo), 1.0)) <= 1e-10
+    assert np.max(np.abs(P - Po)) <= 1e-14
+    assert np.max(np.abs(nr.cpu().numpy() - 1.0)) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_mixer_mode_boundaries_and_large_gamma(api, prec):
+    """beta at 0, pi/4 (tan = 1), pi/2 (cos = 0), negative, beyond pi/2; gamma
+    large enough that gamma * C spans many turns (range reduction)."""
+    n, p = 11, 6
+    Q = workloads.qubo(n, 77)
+    g = np.array([[0.3, 1.7, 40.0, -2.5, 0.0, 3.1]])
+    b = np.array([[0.0, np.pi / 4, np.pi / 2, -0.7, 2.2, np.pi / 4 + 1e-9]])
+    psi, e, _ = api.state(cuda(Q), cuda(g), cuda(b), prec=prec)
+    ref = oracle.state(Q, g[0], b[0])
+    l2 = np.linalg.norm(psi.cpu().numpy()[0, 0].astype(np.complex128) - ref)
+    assert l2 <= TOL_PSI[prec], l2
+    for nq in (17,):
+        Q2 = workloads.qubo(nq, 78)
+        psi2, _, _ = api.state(cuda(Q2), cuda(g), cuda(b), prec=prec)
+        ref2 = oracle.state(Q2, g[0], b[0])
+        l2 = np.linalg.norm(psi2.cpu().numpy()[0, 0].astype(np.complex128) - ref2)
+        assert l2 <= TOL_PSI[prec], l2
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_nonsymmetric_q(api, prec):
+    n, p = 15, 2
+    rng = np.random.default_rng(5)
+    Q = rng.uniform(-1, 1, (n, n))
+    g, b = workloads.params(2, p, 6)
+    e = api.expect(cuda(Q), cuda(g), cuda(b), prec=prec).cpu().numpy()[0]
+    eo, _, _ = oracle.expect(Q, g, b)
+    for s in range(2):
+        assert abs(e[s] - eo[s]) <= TOL_E[prec](eo[s], cmax(Q))
+
+
+def test_deterministic_repeat(api):
+    n, p = 18, 3
+    Q = workloads.qubo(n, 9)
+    g, b = workloads.params(4, p, 10)
+    a1 = api.expect(cuda(Q), cuda(g), cuda(b), prec="c64").cpu().numpy()
+    a2 = api.expect(cuda(Q), cuda(g), cuda(b), prec="c64").cpu().numpy()
+    assert np.array_equal(a1, a2)
