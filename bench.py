@@ -1,0 +1,236 @@
+#!/usr/bin/env python3
+"""Benchmark of the QAOA state-vector hot path on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): one dense
+n = 24 QUBO (symmetric, upper triangle i.i.d. uniform[-1, 1], seed 2), p = 4
+layers, 16 (gamma, beta) parameter sets (gamma ~ U[0, pi], beta ~ U[0, pi/2],
+seed 12), complex64 state with FP64 phase range reduction and FP64 <C>
+reductions.  One step = one qaoa_expect call over all 16 sets: 16 * 4 * 2^24
+amplitude-layer updates, inputs resident in HBM.
+
+Printed: one JSON line with the throughput (amplitude-layer updates/s), the
+achieved HBM bandwidth of the dominant kernel (the forward tile pass) from HIP
+events on its launch stream, a roofline record against MI355X's 8 TB/s, the
+CPU oracle timed on a bounded sample on the host cores, and the numerical
+error of the complex64 form against complex128 and the oracle.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0
+METRIC = ("amplitude-layer updates/s + HBM GB/s; sub-QUBO solves/s with p50/p99 "
+          "latency")
+KERNEL_SRC = os.path.join(ROOT, "paper_2506_10531_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_pass_precision_n24_traffic.json")
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per launch of the forward pass from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sha") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--cpu-sets", type=int, default=8,
+                    help="parameter sets the CPU oracle runs (bounded sample)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the complex128 comparison and error report")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run only a 2 GiB device copy (counter calibration)")
+    return ap.parse_args()
+
+
+def copy_probe():
+    """A plain 2 GiB device-to-device copy: reads 2 GiB and writes 2 GiB, used
+    to scale FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    a = torch.empty(1 << 28, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": a.numel() * 8, "launches": 3}))
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only (--gpus 1); multi-GPU "
+              "runs are not supported", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
+
+    import numpy as np
+    import torch
+
+    from paper_2506_10531_amd import api, workloads
+
+    W = workloads.WORKLOADS["precision_n24"]
+    n, p, S = W["n"], W["p"], W["sets"]
+    prec = args.prec
+    dev = torch.device("cuda:0")
+    Q = workloads.qubo(n, W["q_seed"])
+    g, b = workloads.params(S, p, W["p_seed"])
+    Qd = torch.as_tensor(Q, device=dev)
+    gd = torch.as_tensor(g, device=dev)
+    bd = torch.as_tensor(b, device=dev)
+    ctx = api.Context(0)
+    plan = ctx.plan(prec, 1, n, p, S)
+    el = 8 if prec == "c64" else 16
+    updates_per_step = S * p * (1 << n)
+    floor_bytes_per_step = updates_per_step * 2 * el  # one read + one write per layer
+
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        e = api.expect(Qd, gd, bd, prec=prec, ctx=ctx)
+    torch.cuda.synchronize()
+
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        e = api.expect(Qd, gd, bd, prec=prec, ctx=ctx)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.profile(False)
+    launches, pass_ms, pass_bytes = ctx.profile_read(reset=True)
+    ev_ms = ev0.elapsed_time(ev1)
+
+    ms_per_step = 1e3 * wall / args.steps
+    value = updates_per_step * args.steps / wall
+    avg_launch_ms = pass_ms / max(launches, 1)
+    bytes_per_launch = pass_bytes / max(launches, 1)
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    traffic = load_traffic()
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "amplitude-layer updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == "c64" else "f64",
+        "precision": ("complex64 state, FP64 phase range reduction and FP64 "
+                      "<C>/norm sums" if prec == "c64" else "complex128 state, FP64"),
+        "data": "synthetic",
+        "config": {"workload": "precision_n24: one dense n=24 QUBO, p=4, 16 "
+                               "parameter sets", "n": n, "p": p, "sets": S,
+                   "prec": prec, "q_seed": W["q_seed"], "p_seed": W["p_seed"]},
+        "hbm_GBps": floor_bytes_per_step * args.steps / wall / 1e9,
+        "event_ms_per_step": ev_ms / args.steps,
+        "plan": {"passes": plan["passes"], "sets": plan["sets"],
+                 "tile_qubits": plan["tile_qubits"],
+                 "state_reads": plan["state_reads"],
+                 "state_writes": plan["state_writes"]},
+        "roofline": {
+            "kernel": "fwd_pass_kernel<float>" if prec == "c64" else "fwd_pass_kernel<double>",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": PEAK_HBM_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBPS,
+            "traffic": (traffic if traffic is None else traffic),
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "avg_launch_ms": avg_launch_ms,
+            "launches": launches,
+        },
+    }
+
+    if not args.no_extras:
+        import oracle
+        e_main = e.cpu().numpy()[0]
+        other = "c128" if prec == "c64" else "c64"
+        e_other = api.expect(Qd, gd, bd, prec=other, ctx=ctx).cpu().numpy()[0]
+        # the other precision's throughput on the same workload
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_read(reset=True)
+        t0 = time.perf_counter()
+        k2 = max(3, args.steps // 4)
+        for _ in range(k2):
+            api.expect(Qd, gd, bd, prec=other, ctx=ctx)
+        torch.cuda.synchronize()
+        w2 = time.perf_counter() - t0
+        ctx.profile(False)
+        l2, ms2, by2 = ctx.profile_read(reset=True)
+        ach2 = (by2 / max(l2, 1)) / (ms2 / max(l2, 1) * 1e-3) / 1e9
+        out[f"{other}_form"] = {"value": updates_per_step * k2 / w2,
+                                "achieved_GBps": ach2, "frac": ach2 / PEAK_HBM_GBPS,
+                                "ms_per_step": 1e3 * w2 / k2}
+        C = oracle.cost_table(Q)
+        cmax = float(np.max(np.abs(C)))
+        e64 = e_main if prec == "c64" else e_other
+        e128 = e_other if prec == "c64" else e_main
+        psi64, _, _ = api.state(Qd, gd[:1], bd[:1], prec="c64", ctx=ctx)
+        ref = oracle.state(Q, g[0], b[0])
+        l2err = float(np.linalg.norm(psi64.cpu().numpy()[0, 0].astype(np.complex128) - ref))
+        del psi64
+        out["errors"] = {
+            "max_abs_C": cmax,
+            "c64_vs_c128_expect_max_abs": float(np.max(np.abs(e64 - e128))),
+            "c64_vs_c128_over_maxC": float(np.max(np.abs(e64 - e128)) / cmax),
+            "c64_state_l2_vs_oracle_set0": l2err,
+        }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        k = max(1, min(S, args.cpu_sets))
+        t0 = time.perf_counter()
+        eo, _, _ = oracle.expect(Q, g[:k], b[:k])
+        tc = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": k * p * (1 << n) / tc,
+            "unit": "amplitude-layer updates/s",
+            "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{k} of the {S} parameter sets of the same n=24, p=4 workload "
+                      f"(one oracle call: cost table + {k} x {p} layers), {tc:.1f} s",
+        }
+        if "errors" in out:
+            ee = e_main if prec == "c64" else e_other
+            out["errors"]["c64_vs_oracle_expect_max_abs"] = float(np.max(np.abs(ee[:k] - eo)))
+            ec = e_other if prec == "c64" else e_main
+            out["errors"]["c128_vs_oracle_expect_max_rel"] = float(
+                np.max(np.abs(ec[:k] - eo) / np.maximum(np.abs(eo), 1.0)))
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -429,6 +429,9 @@ __global__ void __launch_bounds__(NT_MAX) fwd_pass_kernel(FwdArgs A) {
 
 struct BwdRoundOps {
   bool xq;       // accumulate sum_q Im <lam|X_q|psi> over the round's qubits
+  double xq_w;   // weight of this round's sum: the butterflies of earlier
+                 // rounds left both tiles without their per-qubit scale
+                 // (|c| or |s| per qubit), so the product lacks its square
   bool scale;    // multiply both tiles by (sr, si) after the butterflies
   double sr, si;
   bool phase;    // then accumulate Im <lam|C|psi> and undo the phase
@@ -462,7 +465,7 @@ __device__ void bwd_round(typename Cx<T>::V* tp, typename Cx<T>::V* tl, int k,
           // Im(conj(lam_v) psi_u) = lx*py - ly*px
           acc += (double)b[v].x * a[u].y - (double)b[v].y * a[u].x;
         }
-      ab += acc;
+      ab = fma(o.xq_w, acc, ab);
     }
 #pragma unroll
     for (int q = 0; q < R; ++q)
@@ -524,11 +527,15 @@ __device__ void bwd_mix(typename Cx<T>::V* tp, typename Cx<T>::V* tl,
   mix_scale(L, d.k - d.mixlo, true, sr, si);
   const T t = (T)(-L.tb);
   double ab = 0.0, ag = 0.0;
+  const double q2 = L.mode == 0 ? L.cb * L.cb : L.sb * L.sb;
+  double w = 1.0;
   for (int g0 = d.mixlo; g0 < d.k; g0 += RB) {
     const int r = min(RB, d.k - g0);
     const bool last = g0 + r >= d.k;
     BwdRoundOps o;
     o.xq = true;
+    o.xq_w = w;
+    for (int q = 0; q < r; ++q) w *= q2;
     o.scale = last;
     o.sr = sr;
     o.si = si;

@@ -1,0 +1,143 @@
+"""GPU parity of the adjoint gradient and of sampling against the oracle.
+
+Gradient tolerances: complex128 within 1e-10 * max(1, max_z |C(z)|) of the
+oracle's adjoint and within 1e-6 relative of central differences (h = 1e-6)
+of the GPU's own complex128 <C>; complex64 within 1e-5 * max_z |C(z)| * p of
+the oracle.  Sampling: every shot equals the oracle's draw unless the oracle's
+u_s * total lies within the state-precision CDF error of an interval boundary
+(1e-9 complex128, 2e-5 complex64); the counted exceptions must be rare.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_10531_amd import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = 0x9E3779B97F4A7C15
+
+
+@pytest.fixture(scope="module")
+def api():
+    assert torch.cuda.is_available()
+    from paper_2506_10531_amd import api as a
+    return a
+
+
+def cuda(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda:0")
+
+
+def cmax(Q):
+    return float(np.max(np.abs(oracle.cost_table(Q))))
+
+
+GRAD_CASES = [("c128", 3, 1), ("c128", 8, 3), ("c128", 12, 2), ("c128", 13, 2),
+              ("c128", 16, 3), ("c128", 18, 2), ("c64", 5, 2), ("c64", 13, 4),
+              ("c64", 14, 2), ("c64", 16, 6), ("c64", 19, 3)]
+
+
+@pytest.mark.parametrize("prec,n,p", GRAD_CASES)
+def test_grad_matches_oracle(api, prec, n, p):
+    B, S = 2, 2
+    Qs = workloads.qubos(B, n, 3000 + n)
+    g, b = workloads.params(S, p, 3100 + n + p, lead=(B,))
+    print(f"grad case prec={prec} n={n} p={p}", flush=True)
+    e, dg, db = api.grad(cuda(Qs), cuda(g), cuda(b), prec=prec)
+    e, dg, db = e.cpu().numpy(), dg.cpu().numpy(), db.cpu().numpy()
+    for bi in range(B):
+        eo, dgo, dbo = oracle.grad(Qs[bi], g[bi], b[bi])
+        cm = cmax(Qs[bi])
+        tol = 1e-10 * max(1.0, cm) if prec == "c128" else 1e-5 * cm * p
+        assert np.max(np.abs(dg[bi] - dgo)) <= tol, (np.max(np.abs(dg[bi] - dgo)), tol)
+        assert np.max(np.abs(db[bi] - dbo)) <= tol, (np.max(np.abs(db[bi] - dbo)), tol)
+        etol = 1e-10 * max(1.0, cm) if prec == "c128" else 1e-5 * cm
+        assert np.max(np.abs(e[bi] - eo)) <= etol
+
+
+@pytest.mark.parametrize("n,p", [(9, 2), (16, 3)])
+def test_grad_matches_central_differences(api, n, p):
+    Q = workloads.qubo(n, 3200 + n)
+    g, b = workloads.params(1, p, 3300 + n)
+    _, dg, db = api.grad(cuda(Q), cuda(g), cuda(b), prec="c128")
+    dg, db = dg.cpu().numpy()[0, 0], db.cpu().numpy()[0, 0]
+    h = 1e-6
+    # all shifted parameter sets in one batched expect call
+    G = np.repeat(g, 4 * p, axis=0)
+    Bt = np.repeat(b, 4 * p, axis=0)
+    for j in range(p):
+        G[4 * j + 0, j] += h
+        G[4 * j + 1, j] -= h
+        Bt[4 * j + 2, j] += h
+        Bt[4 * j + 3, j] -= h
+    e = api.expect(cuda(Q), cuda(G), cuda(Bt), prec="c128").cpu().numpy()[0]
+    for j in range(p):
+        fdg = (e[4 * j] - e[4 * j + 1]) / (2 * h)
+        fdb = (e[4 * j + 2] - e[4 * j + 3]) / (2 * h)
+        assert abs(dg[j] - fdg) <= 1e-6 * max(1.0, abs(fdg)), (j, dg[j], fdg)
+        assert abs(db[j] - fdb) <= 1e-6 * max(1.0, abs(fdb)), (j, db[j], fdb)
+
+
+def test_diff_n16_batch_512(api):
+    """512 dense n = 16 QUBOs, p = 6, both precisions; the oracle checks a
+    sample of 6 problems (first, last and spread)."""
+    W = workloads.WORKLOADS["diff_n16"]
+    B, n, p = W["batch"], W["n"], W["p"]
+    Qs = workloads.qubos(B, n, W["q_seed"])
+    g, b = workloads.params(1, p, W["p_seed"], lead=(B,))
+    Qd, gd, bd = cuda(Qs), cuda(g), cuda(b)
+    e64, dg64, db64 = (x.cpu().numpy() for x in api.grad(Qd, gd, bd, prec="c64"))
+    e128, dg128, db128 = (x.cpu().numpy() for x in api.grad(Qd, gd, bd, prec="c128"))
+    for bi in (0, 1, 101, 255, 400, 511):
+        eo, dgo, dbo = oracle.grad(Qs[bi], g[bi], b[bi])
+        cm = cmax(Qs[bi])
+        assert np.max(np.abs(dg128[bi] - dgo)) <= 1e-10 * cm
+        assert np.max(np.abs(db128[bi] - dbo)) <= 1e-10 * cm
+        assert np.max(np.abs(dg64[bi] - dgo)) <= 1e-5 * cm * p
+        assert np.max(np.abs(db64[bi] - dbo)) <= 1e-5 * cm * p
+        assert abs(e128[bi, 0] - eo[0]) <= 1e-10 * max(1.0, abs(eo[0]))
+
+
+def test_autograd_function(api):
+    n, p, S = 12, 3, 2
+    Q = cuda(workloads.qubo(n, 3400))
+    g0, b0 = workloads.params(S, p, 3401)
+    g = cuda(g0[None]).requires_grad_(True)
+    b = cuda(b0[None]).requires_grad_(True)
+    e = api.QAOAExpect.apply(Q[None], g, b, "c128")
+    w = torch.tensor([[0.5, -2.0]], dtype=torch.float64, device="cuda:0")
+    (e * w).sum().backward()
+    _, dg, db = api.grad(Q, cuda(g0), cuda(b0), prec="c128")
+    assert torch.allclose(g.grad, dg * w[..., None], atol=1e-12)
+    assert torch.allclose(b.grad, db * w[..., None], atol=1e-12)
+
+
+@pytest.mark.parametrize("prec,n,p", [("c128", 6, 2), ("c128", 13, 1), ("c128", 17, 2),
+                                      ("c64", 10, 3), ("c64", 14, 2), ("c64", 18, 2)])
+def test_sampling_matches_oracle_draws(api, prec, n, p):
+    B, shots, seed = 3, 2048, 12345
+    Qs = workloads.qubos(B, n, 3500 + n)
+    g, b = workloads.params(1, p, 3600 + n, lead=(B,))
+    r = api.sample(cuda(Qs), cuda(g[:, 0]), cuda(b[:, 0]), shots, seed, prec=prec)
+    z = r["z"].cpu().numpy().astype(np.uint64)
+    cz = r["cz"].cpu().numpy()
+    bz = r["best_z"].cpu().numpy().astype(np.uint64)
+    bc = r["best_c"].cpu().numpy()
+    ex = r["expect"].cpu().numpy()
+    tol = 1e-9 if prec == "c128" else 2e-5
+    for bi in range(B):
+        seed_b = (seed + bi * shots * GOLDEN) % 2**64
+        o = oracle.sample(Qs[bi], g[bi, 0], b[bi, 0], shots, seed_b)
+        diff = z[bi] != o["z"]
+        # a mismatch is allowed only where the draw sits at a CDF boundary
+        assert np.all(o["gap"][diff] <= tol), o["gap"][diff]
+        assert diff.sum() <= max(2, shots // 200), diff.sum()
+        C = oracle.cost_table(Qs[bi])
+        assert np.allclose(cz[bi], C[z[bi].astype(np.int64)], atol=1e-12)
+        order = np.lexsort((z[bi], cz[bi]))
+        assert bz[bi] == z[bi][order[0]] and bc[bi] == cz[bi][order[0]]
+        eo = oracle.expect(Qs[bi], g[bi], b[bi])[0][0]
+        etol = 1e-10 * max(1.0, abs(eo)) if prec == "c128" else 1e-5 * np.max(np.abs(C))
+        assert abs(ex[bi] - eo) <= etol
