@@ -60,6 +60,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the complex128 comparison and error report")
+    ap.add_argument("--serving-requests", type=int, default=512,
+                    help="requests replayed against the batched solve queue (0: skip)")
+    ap.add_argument("--serving-single", type=int, default=32,
+                    help="requests of the same trace for the one-at-a-time queue")
+    ap.add_argument("--serving-slots", type=int, default=256)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a 2 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -75,6 +80,79 @@ def copy_probe():
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes": a.numel() * 8, "launches": 3}))
+
+
+def serving_leg(requests: int, one_at_a_time: int, max_slots: int, calib: int):
+    """Sub-QUBO solves/s and p50/p99 latency of the solve queue.
+
+    Requests come from one dense N = 1000 QUBO by random decomposition
+    (n ~ U{12..22} sorted variables, principal submatrix), p = 3, 100 Adam
+    evaluations + 1024 shots each, complex64.  A calibration run (all
+    `calib` requests at once) gives the saturated rate mu; the Poisson trace
+    arrives at 0.8 mu and is replayed against the batched queue (all
+    `requests`) and, for its first `one_at_a_time` requests, against the
+    one-request-at-a-time queue.  Latency = done - submit (library clock)."""
+    import threading
+
+    import numpy as np
+
+    from paper_2506_10531_amd import serve, workloads
+
+    W = workloads.WORKLOADS["serving"]
+    p, evals, shots = W["p"], W["evals"], W["shots"]
+    _, reqs = workloads.subqubo_requests(requests, N=W["N"], n_lo=W["n_lo"],
+                                         n_hi=W["n_hi"], seed=W["q_seed"])
+    g0, b0 = workloads.params(requests, p, W["q_seed"] + 7)
+    items = [(Q, g0[i], b0[i], 10_000 + i) for i, (_, Q) in enumerate(reqs)]
+
+    def run(batch, items, arrivals):
+        q = serve.SolveQueue(prec="c64", p=p, evals=evals, shots=shots,
+                             max_slots=max_slots if batch else 1, batched=batch,
+                             max_pending=len(items) + 1)
+        tickets = [None] * len(items)
+
+        def client():
+            t0 = time.perf_counter()
+            for i, (Q, g, b, sd) in enumerate(items):
+                if arrivals is not None:
+                    dt = arrivals[i] - (time.perf_counter() - t0)
+                    if dt > 0:
+                        time.sleep(dt)
+                tickets[i] = q.submit(Q, g, b, sd)
+
+        th = threading.Thread(target=client)
+        th.start()
+        res = []
+        for i in range(len(items)):
+            while tickets[i] is None:
+                time.sleep(0.0005)
+            res.append(q.wait(tickets[i]))
+        th.join()
+        q.close()
+        ok = [r for r in res if r["status"] == 0]
+        lat = np.array([(r["t_done_ns"] - r["t_submit_ns"]) * 1e-6 for r in ok])
+        span = (max(r["t_done_ns"] for r in ok) - min(r["t_submit_ns"] for r in ok)) * 1e-9
+        return dict(solves=len(ok), failed=len(res) - len(ok),
+                    solves_per_s=len(ok) / span, p50_ms=float(np.percentile(lat, 50)),
+                    p99_ms=float(np.percentile(lat, 99)), span_s=span)
+
+    cal = run(True, items[:calib], None)
+    rate = 0.8 * cal["solves_per_s"]
+    arr = workloads.poisson_arrivals(requests, rate, W["arrival_seed"])
+    batched = run(True, items, arr)
+    single = run(False, items[:one_at_a_time], arr[:one_at_a_time])
+    return {
+        "workload": (f"{requests} sub-QUBOs of one dense N={W['N']} QUBO, n~U{{"
+                     f"{W['n_lo']}..{W['n_hi']}}}, p={p}, {evals} Adam evaluations + "
+                     f"{shots} shots each, complex64, Poisson arrivals at 0.8 x the "
+                     f"saturated rate"),
+        "saturated_solves_per_s": cal["solves_per_s"],
+        "arrival_rate_per_s": rate,
+        "batched": batched,
+        "one_at_a_time": dict(single, requests=one_at_a_time,
+                              note="first requests of the same trace"),
+        "max_slots": max_slots,
+    }
 
 
 def main():
@@ -160,7 +238,9 @@ def main():
                  "state_reads": plan["state_reads"],
                  "state_writes": plan["state_writes"]},
         "roofline": {
-            "kernel": "fwd_pass_kernel<float>" if prec == "c64" else "fwd_pass_kernel<double>",
+            "kernel": ("fwd_pass_kernel<double>" if prec == "c128" else
+                       "fwd_pass_kernel<float>" if os.environ.get("DQAOA_FWD_KERNEL") == "lds"
+                       else "fwd14_kernel (complex64 register tile)"),
             "bound": "hbm",
             "achieved": achieved,
             "peak": PEAK_HBM_GBPS,
@@ -229,6 +309,10 @@ def main():
             ec = e_other if prec == "c64" else e_main
             out["errors"]["c128_vs_oracle_expect_max_rel"] = float(
                 np.max(np.abs(ec[:k] - eo) / np.maximum(np.abs(eo), 1.0)))
+    if args.serving_requests > 0:
+        out["serving"] = serving_leg(args.serving_requests, args.serving_single,
+                                     args.serving_slots,
+                                     calib=min(256, args.serving_requests))
     print(json.dumps(out))
 
 

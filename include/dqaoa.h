@@ -154,10 +154,11 @@ typedef struct {
 int qaoa_plan(qaoa_ctx* ctx, int prec, int B, int n, int p, int S, int grad,
               qaoa_plan_info* out);
 
-/* The pass sequence behind qaoa_plan, one record of 9 ints per pass:
+/* The pass sequence behind qaoa_plan, one record of 10 ints per pass:
  * {set, tile_qubits k, contiguous low qubits c, first high tile bit a,
  *  first mixed tile qubit, lead layer (-1: none), first phase layer,
- *  last phase layer (first > last: none), flags}.  A pass applies the mixer
+ *  last phase layer (first > last: none), flags, kernel (0: LDS tile,
+ *  1/2: register tile with 14 qubits)}.  A pass applies the mixer
  * of the lead layer to its set, then for each phase layer j the phase of
  * layer j and the mixer of layer j on its set.  Tile qubits are global bits
  * [0, c) and [a, a + k - c) (all of [0, k) when c == k); the mixed tile

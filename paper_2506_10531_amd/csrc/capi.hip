@@ -11,6 +11,7 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -136,6 +137,105 @@ bool make_plan(int n, int p, int kmax, int cpref, Plan* P) {
   return true;
 }
 
+// Register-tile plan: the same pass sequence as make_plan, with every tile
+// holding 14 qubits.  Set 0 mixes [0, 14); the remaining qubits [14, n) are
+// split into runs of at most 10, and set i's tile is the 4 low bits plus the
+// 10-bit run [a, a + 10) that ends at its mixed run (or at n), so it carries
+// (does not mix) any of those 10 bits below its own run.
+bool make_plan_reg14(int n, int p, Plan* P) {
+  *P = Plan();
+  P->K = 14;
+  if (n < 15 || n > 34 || p < 1 || p > 64) return false;
+  const int m = 1 + (n - 14 + 9) / 10;
+  const int rest = n - 14, q = m - 1;
+  int lo[4] = {0}, hi[4] = {0}, a[4] = {0};
+  lo[0] = 0;
+  hi[0] = 14;
+  int cur = 14;
+  for (int i = 1; i < m; ++i) {
+    const int run = rest / q + (i - 1 < rest % q ? 1 : 0);
+    lo[i] = cur;
+    hi[i] = cur + run;
+    cur += run;
+    a[i] = hi[i] - 10 < 4 ? 4 : hi[i] - 10;
+    if (a[i] + 10 > n) a[i] = n - 10;
+  }
+  P->sets = m;
+  P->c = 4;
+  for (int i = 0; i < m; ++i) {
+    P->k[i] = 14;
+    P->a[i] = a[i];
+  }
+  auto desc = [&](int set, int lead, int ja, int jb) {
+    PassDesc d{};
+    d.n = n;
+    d.set = set;
+    d.lead = lead;
+    d.ja = ja;
+    d.jb = jb;
+    d.k = 14;
+    if (set == 0) {
+      d.c = 14;
+      d.a = 14;
+      d.mixlo = 0;
+      d.kind = 1;
+    } else {
+      d.c = 4;
+      d.a = a[set];
+      d.mixlo = 4 + (lo[set] - a[set]);
+      d.kind = 2;
+    }
+    return d;
+  };
+  auto order = [&](int j, int i) { return (j % 2 == 0) ? i : m - 1 - i; };
+  int np = 0;
+  P->pass[np++] = desc(order(0, 0), -1, 0, 0);
+  for (int j = 0; j < p; ++j) {
+    for (int i = 1; i <= m - 2; ++i) P->pass[np++] = desc(order(j, i), j, 1, 0);
+    if (j < p - 1) P->pass[np++] = desc(order(j, m - 1), j, j + 1, j + 1);
+    else P->pass[np++] = desc(order(j, m - 1), j, 1, 0);
+  }
+  // pending mixer scales at the start of every pass
+  int pn = 0, pl[3] = {0}, pm[3] = {0};
+  for (int i = 0; i < np; ++i) {
+    PassDesc& d = P->pass[i];
+    d.flags = (i == 0 ? F_INIT : 0) | (i < np - 1 ? F_WRITE : F_REDUCE);
+    if (pn > 2) return false;
+    d.pend_n = pn;
+    for (int t = 0; t < pn; ++t) {
+      d.pend_layer[t] = pl[t];
+      d.pend_m[t] = pm[t];
+    }
+    const int mset = hi[d.set] - lo[d.set];
+    if (d.ja <= d.jb) {  // the phase applies every pending factor
+      pn = 1;
+      pl[0] = d.jb;
+      pm[0] = mset;
+    } else {
+      pl[pn] = d.lead;
+      pm[pn] = mset;
+      ++pn;
+    }
+  }
+  P->npass = np;
+  return true;
+}
+
+// The register-tile kernel serves complex64 forward evaluations with n >= 15;
+// DQAOA_FWD_KERNEL=lds selects the LDS-tile kernel for every pass instead.
+static bool use_reg14(int op, int prec, int n) {
+  static const bool off = [] {
+    const char* v = getenv("DQAOA_FWD_KERNEL");
+    return v && strcmp(v, "lds") == 0;
+  }();
+  return !off && op != OP_GRAD && prec == QAOA_C64 && n >= 15 && n <= 34;
+}
+
+bool choose_plan(int op, int prec, int n, int p, Plan* P) {
+  if (use_reg14(op, prec, n)) return make_plan_reg14(n, p, P);
+  return make_plan(n, p, kmax_for(prec, op == OP_GRAD), cpref_for(prec), P);
+}
+
 int kmax_for(int prec, bool two_tiles) {
   const int k = prec == QAOA_C128 ? 13 : 14;
   return two_tiles ? k - 1 : k;
@@ -159,7 +259,7 @@ int make_layout(int op, int prec, int B, int n, int p, int S, int shots,
   L->n = n;
   L->p = p;
   L->S = S;
-  if (!make_plan(n, p, kmax_for(prec, grad), cpref_for(prec), &L->plan))
+  if (!choose_plan(op, prec, n, p, &L->plan))
     return set_error(QAOA_ERR_UNSUPPORTED, "no pass plan for n = %d", n);
   L->nstates = (size_t)B * S;
   size_t amps;
@@ -230,8 +330,12 @@ int run_forward(const Layout& L, char* base, const double* Q,
     if (d.flags & F_WRITE) bytes += sb;
     if (d.flags & F_PROBS) bytes += sb / 2;
     TimerScope ts(tm, s, bytes);
-    e = launch_fwd_pass(L.prec, d, (int)L.nstates, L.S, L.p, state,
-                        (last && psi) ? psi : state, stride, W, coef, part, probs, s);
+    if (d.kind)
+      e = launch_fwd14_pass(d, (int)L.nstates, L.S, L.p, state,
+                            (last && psi) ? psi : state, stride, W, coef, part, probs, s);
+    else
+      e = launch_fwd_pass(L.prec, d, (int)L.nstates, L.S, L.p, state,
+                          (last && psi) ? psi : state, stride, W, coef, part, probs, s);
     if (e != hipSuccess) return hip_error(e, "forward pass");
   }
   return QAOA_OK;
@@ -544,13 +648,13 @@ int qaoa_plan_passes(qaoa_ctx* ctx, int prec, int n, int p, int grad, int* out,
   if (!npass || (!out && max_passes > 0))
     return set_error(QAOA_ERR_INVALID_ARG, "out/npass is NULL");
   Plan P;
-  if (!make_plan(n, p, kmax_for(prec, grad != 0), cpref_for(prec), &P))
+  if (!choose_plan(grad ? OP_GRAD : OP_EXPECT, prec, n, p, &P))
     return set_error(QAOA_ERR_UNSUPPORTED, "no pass plan for n = %d", n);
   *npass = P.npass;
   for (int i = 0; i < P.npass && i < max_passes; ++i) {
     const PassDesc& d = P.pass[i];
-    const int rec[9] = {d.set, d.k, d.c, d.a, d.mixlo, d.lead, d.ja, d.jb, d.flags};
-    for (int f = 0; f < 9; ++f) out[9 * i + f] = rec[f];
+    const int rec[10] = {d.set, d.k, d.c, d.a, d.mixlo, d.lead, d.ja, d.jb, d.flags, d.kind};
+    for (int f = 0; f < 10; ++f) out[10 * i + f] = rec[f];
   }
   return QAOA_OK;
 }

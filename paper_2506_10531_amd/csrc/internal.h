@@ -36,6 +36,16 @@ struct PassDesc {
   int lead, ja, jb;
   int flags;
   int set;     // qubit set index (planning bookkeeping)
+  // Register-tile kernel (complex64, 14-qubit tiles) only: kind 1 = tile
+  // [0, 14) fully mixed, kind 2 = tile [0, 4) + [a, a + 10) mixing local
+  // bits [mixlo, 14); 0 = the LDS-tile kernel.  The register-tile kernel
+  // leaves each mixer's scalar factor (c^m or (i s)^m) pending and folds it
+  // into the next phase; pend_* list the mixer ops (layer, qubit count)
+  // whose factors are still pending when this pass starts.
+  int kind;
+  int pend_n;
+  int pend_layer[2];
+  int pend_m[2];
 };
 
 enum PassFlags {
@@ -59,6 +69,15 @@ struct Plan {
 // Builds the pass sequence.  kmax: qubits per LDS tile (13/14 for one
 // complex128/complex64 tile, one less when two tiles share LDS).
 bool make_plan(int n, int p, int kmax, int cpref, Plan* out);
+// Plan for the register-tile kernel (complex64, n >= 15): every tile has 14
+// qubits; set 0 = [0, 14), set i >= 1 = [0, 4) + a run of 10 high bits of
+// which it mixes its share of [14, n).
+bool make_plan_reg14(int n, int p, Plan* out);
+
+hipError_t launch_fwd14_pass(const PassDesc& d, int nstates, int S, int p,
+                             const void* in, void* out, uint64_t state_stride,
+                             const double* W, const LayerCoef* coef,
+                             double* part, void* probs, hipStream_t stream);
 
 // ---- launchers (kernels.hip) ---------------------------------------------
 // prec: 0 = complex128, 1 = complex64.

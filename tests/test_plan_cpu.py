@@ -22,12 +22,12 @@ def hctx():
 
 
 def passes(h, prec, n, p, grad):
-    buf = (ctypes.c_int * (9 * 400))()
+    buf = (ctypes.c_int * (10 * 400))()
     np_ = ctypes.c_int()
     rc = _lib.load().qaoa_plan_passes(h, prec, n, p, grad, buf, 400, ctypes.byref(np_))
     assert rc == 0, _lib.load().qaoa_last_error()
-    a = np.array(buf[: 9 * np_.value]).reshape(-1, 9)
-    keys = ["set", "k", "c", "a", "mixlo", "lead", "ja", "jb", "flags"]
+    a = np.array(buf[: 10 * np_.value]).reshape(-1, 10)
+    keys = ["set", "k", "c", "a", "mixlo", "lead", "ja", "jb", "flags", "kind"]
     return [dict(zip(keys, map(int, r))) for r in a]
 
 
@@ -48,9 +48,13 @@ CASES = [(prec, n, p, g) for prec in (0, 1) for g in (0, 1)
 @pytest.mark.parametrize("prec,n,p,grad", CASES)
 def test_plan_geometry_and_semantics(hctx, prec, n, p, grad):
     kmax = (13 if prec == 0 else 14) - (1 if grad else 0)
+    reg14 = prec == 1 and not grad and n >= 15
     ps = passes(hctx, prec, n, p, grad)
     for i, d in enumerate(ps):
         assert 1 <= d["k"] <= min(kmax, n)
+        assert (d["kind"] != 0) == reg14
+        if reg14:
+            assert d["k"] == 14 and d["kind"] == (1 if d["set"] == 0 else 2)
         tb = tile_bits(d, n)
         assert len(tb) == d["k"] and len(set(tb)) == d["k"]
         assert all(0 <= b < n for b in tb)
