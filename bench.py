@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBPS = 8000.0
 METRIC = ("amplitude-layer updates/s + HBM GB/s; sub-QUBO solves/s with p50/p99 "
           "latency")
-KERNEL_SRC = os.path.join(ROOT, "paper_2506_10531_amd", "csrc", "kernels.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_2506_10531_amd", "csrc", "fwd14.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_pass_precision_n24_traffic.json")
 
 
@@ -76,10 +76,16 @@ def copy_probe():
     import torch
     a = torch.empty(1 << 28, dtype=torch.float64, device="cuda:0").fill_(1.0)
     b = torch.empty_like(a)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.copy_(a)
+    t0.record()
     for _ in range(3):
         b.copy_(a)
+    t1.record()
     torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes": a.numel() * 8, "launches": 3}))
+    ms = t0.elapsed_time(t1) / 3
+    print(json.dumps({"copy_probe_bytes": a.numel() * 8, "launches": 4,
+                      "copy_GBps": 2 * a.numel() * 8 / (ms * 1e-3) / 1e9}))
 
 
 def serving_leg(requests: int, one_at_a_time: int, max_slots: int, calib: int):

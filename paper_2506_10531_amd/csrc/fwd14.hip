@@ -3,27 +3,35 @@
 // Same pass structure as the LDS-tile pass in kernels.hip (a layer's mixer
 // split into commuting qubit sets; the pass finishing layer j on a set also
 // applies the phase of layer j+1 and starts layer j+1, Eq. (2) of the paper),
-// but the 2^14-amplitude tile lives in registers: 512 threads x 32 amplitudes
-// (5 "register" tile bits per thread; 6 lane bits; 3 wave bits).  LDS is only
-// used to move tile bits between registers and lanes/waves (transposes), in
-// two 64 KiB halves split on tile bit 0 (a register bit in every layout), so
-// two work-groups fit in one CU's 160 KiB and overlap each other's memory and
-// compute phases.
+// but the 2^14-amplitude tile lives in registers: 256 threads (4 waves) x 64
+// amplitudes, i.e. 6 "register" tile bits per thread, 6 lane bits and 2 wave
+// bits.  LDS only moves tile bits between registers and lanes/waves
+// (transposes), one 64 KiB half at a time (halves split on tile bit 0, a
+// register bit in every layout), so a work-group needs about 73 KiB and two
+// share a CU: while one waits at a barrier or on memory, the other computes.
 //
-// A half-mixer (the mixer of one layer on one qubit set) visits three layouts;
-// in each, the butterflies of its register bits run in registers and those of
-// lane bits 0 and 1 run across lanes with DPP quad permutes.  The butterfly is
-// the tan/cot form (two FMAs per component); the scalar c^m or (i s)^m of each
-// half-mixer is left pending and folded into the next phase multiply, or into
-// the outputs of the last pass.
+// A half-mixer (the mixer of one layer on the pass's qubit set) visits two
+// layouts: in each, the butterflies of its register bits run in registers and
+// those of lane bits 0 and 1 run across lanes with DPP quad permutes, so 6 + 2
+// tile bits can be mixed per layout and one transpose per half-mixer does.
+// The butterfly is the tan/cot form (two FMAs per component); the scalar c^m
+// or (i s)^m of each half-mixer is left pending and folded into the next phase
+// multiply, or into the outputs of the last pass.  Both forms run the same
+// arithmetic, (a0, a1) -> (a0 + i t a1, a1 + i t a0): cos b I + i sin b X
+// equals i sin b X (I + i t X) with t = -cot b, and the trailing X on every
+// mixed qubit commutes with the whole half-mixer, so it becomes a relabelling
+// of the tile.  The transpose inside the half-mixer applies it to tile bits
+// 1..13 by XORing its LDS write address; a flip of tile bit 0 (only set 0
+// mixes it) stays pending: the phase tables are built for the flipped bit and
+// the stores swap the two amplitudes of each register pair.
 //
 // Phase: C(z) = cfix(thread) + sum_s r_s g_s(thread) + K(r) over the thread's
-// 5 register bits r.  cfix and g come from per-tile tables (lane part, wave
-// part, lane-wave cross terms) built in LDS in FP64; the angles gamma*cfix/2pi
-// and gamma*g_s/2pi are range-reduced in FP64, and the 32 phase factors are
-// the products of the 6 resulting unit complex numbers and of the per-tile
-// factors e^{-i gamma K(r)}.  The last pass accumulates <C> in FP64 from the
-// same decomposition.
+// 6 register bits r.  cfix and g come from per-tile FP64 tables in LDS (lane
+// part, wave part, lane-wave cross terms); the angles gamma*cfix/2pi and
+// gamma*g_s/2pi are range-reduced in FP64, and the 64 phase factors are the
+// products of the 7 resulting unit complex numbers and of the per-tile factors
+// e^{-i gamma K(r)}.  The last pass accumulates <C> in FP64 from the same
+// decomposition.
 #include "internal.h"
 
 #include <hip/hip_runtime.h>
@@ -33,47 +41,42 @@
 namespace dq {
 namespace {
 
-constexpr int NT14 = 512;
-constexpr int HALF = 1 << 13;                // amplitudes per LDS half
-constexpr int PHYS = HALF + (HALF >> 4);     // padded slots per half
+constexpr int NT14 = 256;
+constexpr int HALF = 1 << 13;  // amplitudes per LDS half
 
-// Layouts: the tile bit held by register slots 0..4, lane slots 0..5 and wave
-// slots 0..2.  Register slot 0 is tile bit 0 everywhere (the transpose pivot).
-//   0: A  (load/store)   1: B (set 0)   2: C (set 0, phase)
-//   3: B' (other sets)   4: C' (other sets, phase)
+// Layouts: the tile bit held by register slots 0..5, lane slots 0..5 and wave
+// slots 0..1.  Register slot 0 is tile bit 0 everywhere (the transpose pivot).
+//   0: A   load/store layout (lane slots = tile bits 1..6: 1 KiB runs)
+//   1: B   phase layout of qubit set 0 (A and B together mix tile bits 0..13)
+//   2: B'  phase layout of the other sets (A and B' together mix bits 4..13)
 __host__ __device__ constexpr int reg_bit(int L, int s) {
-  constexpr int t[5][5] = {{0, 7, 8, 9, 10},
-                           {0, 3, 4, 5, 6},
-                           {0, 11, 12, 13, 5},
-                           {0, 4, 5, 6, 11},
-                           {0, 12, 13, 5, 6}};
+  constexpr int t[3][6] = {{0, 7, 8, 9, 10, 11}, {0, 7, 3, 4, 5, 6}, {0, 7, 4, 5, 6, 12}};
   return t[L][s];
 }
 __host__ __device__ constexpr int lane_bit(int L, int s) {
-  constexpr int t[5][6] = {{1, 2, 3, 4, 5, 6},
-                           {1, 2, 7, 8, 9, 10},
-                           {1, 2, 3, 4, 6, 7},
-                           {1, 2, 7, 8, 3, 9},
-                           {1, 2, 3, 4, 7, 8}};
+  constexpr int t[3][6] = {{1, 2, 3, 4, 5, 6}, {12, 13, 1, 2, 8, 9}, {13, 1, 2, 3, 8, 9}};
   return t[L][s];
 }
 __host__ __device__ constexpr int wave_bit(int L, int s) {
-  constexpr int t[5][3] = {{11, 12, 13}, {11, 12, 13}, {8, 9, 10},
-                           {10, 12, 13}, {9, 10, 11}};
+  constexpr int t[3][2] = {{12, 13}, {10, 11}, {10, 11}};
   return t[L][s];
 }
 
-// Padded LDS slot of a half index (tile index without bit 0): one pad slot
-// per 16.  Additive over disjoint bit sets, and every layout's lane slots 0..3
-// land on half-index bits whose padded strides are 1, 2, 4 and 8 slots (mod
-// 16), so every 16-lane group of an access hits 16 distinct 8-byte banks.
-__host__ __device__ constexpr uint32_t phys(uint32_t h) { return h + (h >> 4); }
+// XOR swizzle of a half index h (tile index without bit 0): the low 4 bits
+// (an 8-byte bank within a 128-byte row) are XORed with a linear function of
+// the higher bits chosen so that in every layout lane slots 0..3 land on 4
+// independent bank bits, and each 16-lane group of an access hits 16 banks.
+// Linear over GF(2): swz(a ^ b) = swz(a) ^ swz(b).
+__host__ __device__ constexpr uint32_t swz(uint32_t h) {
+  return h ^ (((h >> 4) & 15u) ^ ((h >> 8) & 7u) ^ (((h >> 11) & 1u) << 2) ^
+              (((h >> 12) & 1u) << 3));
+}
 
-// Half-index offset of register index r' (register slots 1..4).
+// Half index of register index r' (register slots 1..5).
 template <int L>
 __host__ __device__ constexpr uint32_t reg_off(int rp) {
   uint32_t l = 0;
-  for (int s = 1; s < 5; ++s)
+  for (int s = 1; s < 6; ++s)
     if ((rp >> (s - 1)) & 1) l |= 1u << reg_bit(L, s);
   return l >> 1;
 }
@@ -84,7 +87,7 @@ __device__ __forceinline__ uint32_t thread_bits(int lane, int wave) {
 #pragma unroll
   for (int s = 0; s < 6; ++s) l |= (uint32_t)((lane >> s) & 1) << lane_bit(L, s);
 #pragma unroll
-  for (int s = 0; s < 3; ++s) l |= (uint32_t)((wave >> s) & 1) << wave_bit(L, s);
+  for (int s = 0; s < 2; ++s) l |= (uint32_t)((wave >> s) & 1) << wave_bit(L, s);
   return l;
 }
 
@@ -96,26 +99,29 @@ __device__ __forceinline__ uint64_t dep14(uint32_t l, int kind, int a) {
 }
 
 // Barrier for LDS hand-offs only: the fence is restricted to the local
-// address space, so it waits for this wave's LDS accesses but not for the
-// global loads of the next tile that are still in flight.
+// address space, so it waits for this wave's LDS accesses but not for global
+// loads still in flight.
 __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Move the tile from layout X to layout Y through LDS, one half at a time.
+// Move the tile from layout X to layout Y through LDS, one half at a time;
+// fx (a swizzled half-index mask) relabels the tile: the amplitude at tile
+// index l moves to l ^ (fx's tile bits).
 template <int X, int Y>
-__device__ __forceinline__ void transpose(float2 (&v)[32], float2* buf, int lane, int wave) {
-  const uint32_t bx = phys(thread_bits<X>(lane, wave) >> 1);
-  const uint32_t by = phys(thread_bits<Y>(lane, wave) >> 1);
+__device__ __forceinline__ void transpose(float2 (&v)[64], float2* buf, int lane, int wave,
+                                          uint32_t fx) {
+  const uint32_t bx = swz(thread_bits<X>(lane, wave) >> 1) ^ fx;
+  const uint32_t by = swz(thread_bits<Y>(lane, wave) >> 1);
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
 #pragma unroll
-    for (int rp = 0; rp < 16; ++rp) buf[bx + phys(reg_off<X>(rp))] = v[(rp << 1) | h];
+    for (int rp = 0; rp < 32; ++rp) buf[bx ^ swz(reg_off<X>(rp))] = v[(rp << 1) | h];
     lds_barrier();
 #pragma unroll
-    for (int rp = 0; rp < 16; ++rp) v[(rp << 1) | h] = buf[by + phys(reg_off<Y>(rp))];
+    for (int rp = 0; rp < 32; ++rp) v[(rp << 1) | h] = buf[by ^ swz(reg_off<Y>(rp))];
     lds_barrier();
   }
 }
@@ -133,7 +139,7 @@ __device__ __forceinline__ float dpp_x2(float x) {
 template <int L>
 __host__ __device__ constexpr uint32_t layout_mixable() {
   uint32_t m = 0;
-  for (int s = 0; s < 5; ++s) m |= 1u << reg_bit(L, s);
+  for (int s = 0; s < 6; ++s) m |= 1u << reg_bit(L, s);
   m |= 1u << lane_bit(L, 0);
   m |= 1u << lane_bit(L, 1);
   return m;
@@ -146,7 +152,7 @@ __host__ __device__ constexpr uint32_t layout_mixable() {
 template <int L, uint32_t DONE, int MIXLO>
 __host__ __device__ constexpr unsigned reg_mask() {
   unsigned m = 0;
-  for (int s = 0; s < 5; ++s) {
+  for (int s = 0; s < 6; ++s) {
     const int b = reg_bit(L, s);
     if (!((DONE >> b) & 1u) && b >= MIXLO) m |= 1u << s;
   }
@@ -162,63 +168,64 @@ __host__ __device__ constexpr unsigned dpp_mask() {
   return m;
 }
 
-template <int MODE, unsigned RM, unsigned DM>
-__device__ __forceinline__ void mix_round(float2 (&v)[32], float t) {
+// (a0, a1) -> (a0 + i t a1, a1 + i t a0) on every selected bit.
+template <unsigned RM, unsigned DM>
+__device__ __forceinline__ void mix_round(float2 (&v)[64], float t) {
 #pragma unroll
-  for (int s = 0; s < 5; ++s) {
+  for (int s = 0; s < 6; ++s) {
     if (!((RM >> s) & 1u)) continue;
 #pragma unroll
-    for (int r = 0; r < 32; ++r) {
+    for (int r = 0; r < 64; ++r) {
       if ((r >> s) & 1) continue;
       float2& a0 = v[r];
       float2& a1 = v[r | (1 << s)];
       const float x0 = a0.x, y0 = a0.y, x1 = a1.x, y1 = a1.y;
-      if (MODE == 0) {
-        a0.x = fmaf(-t, y1, x0);
-        a0.y = fmaf(t, x1, y0);
-        a1.x = fmaf(-t, y0, x1);
-        a1.y = fmaf(t, x0, y1);
-      } else {
-        a0.x = fmaf(t, y0, x1);
-        a0.y = fmaf(-t, x0, y1);
-        a1.x = fmaf(t, y1, x0);
-        a1.y = fmaf(-t, x1, y0);
-      }
+      a0.x = fmaf(-t, y1, x0);
+      a0.y = fmaf(t, x1, y0);
+      a1.x = fmaf(-t, y0, x1);
+      a1.y = fmaf(t, x0, y1);
+      // bound the butterflies in flight (each needs fresh registers until
+      // both of its inputs are dead)
+      if ((r & 15) == 14 || (r & 15) == 15) __builtin_amdgcn_sched_barrier(0);
     }
   }
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     if (!((DM >> s) & 1u)) continue;
 #pragma unroll
-    for (int r = 0; r < 32; ++r) {
+    for (int r = 0; r < 64; ++r) {
       const float x = v[r].x, y = v[r].y;
       const float xp = s == 0 ? dpp_x1(x) : dpp_x2(x);
       const float yp = s == 0 ? dpp_x1(y) : dpp_x2(y);
-      if (MODE == 0) {
-        v[r].x = fmaf(-t, yp, x);
-        v[r].y = fmaf(t, xp, y);
-      } else {
-        v[r].x = fmaf(t, y, xp);
-        v[r].y = fmaf(-t, x, yp);
-      }
+      v[r].x = fmaf(-t, yp, x);
+      v[r].y = fmaf(t, xp, y);
       // keep the DPP temporaries of only a few amplitudes live at a time
       if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
 
-// One half-mixer (the mixer of one layer on the pass's qubit set): rounds in
-// layouts X, Y, Z with transposes X -> Y -> Z between them.
-template <int MODE, int X, int Y, int Z, int MIXLO>
-__device__ __forceinline__ void half_mixer(float2 (&v)[32], float2* buf, int lane, int wave,
-                                           float t) {
+// One half-mixer: a round in layout X, a transpose X -> Y (with the
+// relabelling fx), a round in Y.
+template <int X, int Y, int MIXLO>
+__device__ __forceinline__ void half_mixer(float2 (&v)[64], float2* buf, int lane, int wave,
+                                           float t, uint32_t fx) {
   constexpr uint32_t D1 = layout_mixable<X>();
-  constexpr uint32_t D2 = D1 | layout_mixable<Y>();
-  mix_round<MODE, reg_mask<X, 0, MIXLO>(), dpp_mask<X, 0, MIXLO>()>(v, t);
-  transpose<X, Y>(v, buf, lane, wave);
-  mix_round<MODE, reg_mask<Y, D1, MIXLO>(), dpp_mask<Y, D1, MIXLO>()>(v, t);
-  transpose<Y, Z>(v, buf, lane, wave);
-  mix_round<MODE, reg_mask<Z, D2, MIXLO>(), dpp_mask<Z, D2, MIXLO>()>(v, t);
+  mix_round<reg_mask<X, 0, MIXLO>(), dpp_mask<X, 0, MIXLO>()>(v, t);
+  transpose<X, Y>(v, buf, lane, wave, fx);
+  mix_round<reg_mask<Y, D1, MIXLO>(), dpp_mask<Y, D1, MIXLO>()>(v, t);
+}
+
+// Arithmetic parameter of a half-mixer and its relabelling mask (the mixed
+// tile bits [MIXLO, 14) without bit 0, as a swizzled half index).
+template <int MIXLO>
+__device__ __forceinline__ float mix_t(const LayerCoef& L) {
+  return L.mode == 0 ? (float)L.tb : -(float)L.tb;
+}
+template <int MIXLO>
+__device__ __forceinline__ uint32_t mix_fx(const LayerCoef& L) {
+  constexpr uint32_t mh = ((0x3FFFu >> MIXLO) << MIXLO) >> 1;
+  return L.mode == 0 ? 0u : swz(mh);
 }
 
 // Complex helpers.
@@ -232,7 +239,8 @@ __device__ __forceinline__ float2 unit(double rev) {  // e^{-i 2 pi rev}
   return make_float2(c, -s);
 }
 
-// Mixer scalar of one half-mixer: c^m (mode 0) or (i s)^m (mode 1).
+// Mixer scalar of one half-mixer: c^m (mode 0) or (i s)^m (mode 1),
+// multiplied into (re, im).
 __device__ __forceinline__ void half_scale(const LayerCoef& L, int m, double& re, double& im) {
   double r = 1.0, i = 0.0;
   if (L.mode == 0) {
@@ -251,7 +259,7 @@ __device__ __forceinline__ void half_scale(const LayerCoef& L, int m, double& re
 
 struct F14Args {
   PassDesc d;
-  int S, p, nstates;
+  int S, p;
   const float2* in;
   float2* out;
   uint64_t stride;
@@ -261,21 +269,21 @@ struct F14Args {
   float* probs;
 };
 
-// Per-tile tables for the phase layout PL (FP64), 512 entries:
-//   Ll[64]   energy of the lane bits alone (with their block fields)
-//   Gl[5][64] field of the lane bits on register slot s
-//   Lw[8]    energy of the wave bits alone
-//   Fw[6][8] coupling of lane slot i to the wave bits
-//   Gw[5][8] field of the wave bits on register slot s
-//   Kr[32]   couplings among the register bits
+// Per-tile tables for the phase layout PL (FP64):
+//   Ll[64]    energy of the lane bits alone (with their block fields)
+//   Gl[6][64] field of the lane bits on register slot s
+//   Lw[4]     energy of the wave bits alone
+//   Fw[6][4]  coupling of lane slot i to the wave bits
+//   Gw[6][4]  field of the wave bits on register slot s
+//   Kr[64]    couplings among the register bits
 struct Tables {
-  double Ll[64], Gl[5][64], Lw[8], Fw[6][8], Gw[5][8], Kr[32];
+  double Ll[64], Gl[6][64], Lw[4], Fw[6][4], Gw[6][4], Kr[64];
 };
+constexpr int NTAB = 64 + 6 * 64 + 4 + 6 * 4 + 6 * 4 + 64;
 
 template <int PL>
-__device__ __forceinline__ void build_tables(Tables* T, const double* fl, const double* Wl, int tid) {
-  // every thread fills at most one entry (512 entries in total)
-  int e = tid;
+__device__ __forceinline__ void table_entry(Tables* T, const double* fl, const double* Wl,
+                                            int e) {
   if (e < 64) {
     double s = 0.0;
     for (int i = 0; i < 6; ++i)
@@ -289,7 +297,7 @@ __device__ __forceinline__ void build_tables(Tables* T, const double* fl, const 
     return;
   }
   e -= 64;
-  if (e < 320) {
+  if (e < 6 * 64) {
     const int sl = e >> 6, x = e & 63, br = reg_bit(PL, sl);
     double s = 0.0;
     for (int i = 0; i < 6; ++i)
@@ -297,10 +305,10 @@ __device__ __forceinline__ void build_tables(Tables* T, const double* fl, const 
     T->Gl[sl][x] = s;
     return;
   }
-  e -= 320;
-  if (e < 8) {
+  e -= 6 * 64;
+  if (e < 4) {
     double s = 0.0;
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 2; ++i)
       if ((e >> i) & 1) {
         const int bi = wave_bit(PL, i);
         s += fl[bi];
@@ -310,28 +318,28 @@ __device__ __forceinline__ void build_tables(Tables* T, const double* fl, const 
     T->Lw[e] = s;
     return;
   }
-  e -= 8;
-  if (e < 48) {
-    const int li = e >> 3, y = e & 7, bl = lane_bit(PL, li);
+  e -= 4;
+  if (e < 6 * 4) {
+    const int li = e >> 2, y = e & 3, bl = lane_bit(PL, li);
     double s = 0.0;
-    for (int j = 0; j < 3; ++j)
+    for (int j = 0; j < 2; ++j)
       if ((y >> j) & 1) s += Wl[bl * 14 + wave_bit(PL, j)];
     T->Fw[li][y] = s;
     return;
   }
-  e -= 48;
-  if (e < 40) {
-    const int sl = e >> 3, y = e & 7, br = reg_bit(PL, sl);
+  e -= 6 * 4;
+  if (e < 6 * 4) {
+    const int sl = e >> 2, y = e & 3, br = reg_bit(PL, sl);
     double s = 0.0;
-    for (int j = 0; j < 3; ++j)
+    for (int j = 0; j < 2; ++j)
       if ((y >> j) & 1) s += Wl[br * 14 + wave_bit(PL, j)];
     T->Gw[sl][y] = s;
     return;
   }
-  e -= 40;
-  if (e < 32) {
+  e -= 6 * 4;
+  if (e < 64) {
     double s = 0.0;
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 6; ++i)
       if ((e >> i) & 1)
         for (int j = 0; j < i; ++j)
           if ((e >> j) & 1) s += Wl[reg_bit(PL, i) * 14 + reg_bit(PL, j)];
@@ -339,49 +347,65 @@ __device__ __forceinline__ void build_tables(Tables* T, const double* fl, const 
   }
 }
 
-// The thread's cfix and fields g_s in the phase layout (FP64).
+// The thread's cfix and fields g_s in the phase layout (FP64).  Branch-free,
+// so that it does not split the straight-line code around it.
 template <int PL>
 __device__ __forceinline__ void thread_energy(const Tables* T, const double* fl, double cblk,
-                                              int lane, int wave, double& cfix, double (&g)[5]) {
+                                              int lane, int wave, double& cfix, double (&g)[6]) {
   double c = cblk + T->Lw[wave] + T->Ll[lane];
 #pragma unroll
-  for (int i = 0; i < 6; ++i)
-    if ((lane >> i) & 1) c += T->Fw[i][wave];
+  for (int i = 0; i < 6; ++i) {
+    const double f = T->Fw[i][wave];
+    c += ((lane >> i) & 1) ? f : 0.0;
+  }
   cfix = c;
 #pragma unroll
-  for (int s = 0; s < 5; ++s) g[s] = fl[reg_bit(PL, s)] + T->Gl[s][lane] + T->Gw[s][wave];
+  for (int s = 0; s < 6; ++s) g[s] = fl[reg_bit(PL, s)] + T->Gl[s][lane] + T->Gw[s][wave];
 }
 
-// Phase of layer `L` on the 32 register amplitudes, times the pending mixer
-// scalar (sr, si).
+// Per-thread phase factors of one layer: f0 = e^{-i gamma cfix} times the
+// pending mixer scalar, fs[s] = e^{-i gamma g_s}.
+struct PhaseF {
+  float2 f0, fs[6];
+};
 template <int PL>
-__device__ __forceinline__ void apply_phase(float2 (&v)[32], const Tables* T, const float2* KF,
-                                            const double* fl, double cblk, int lane, int wave,
-                                            double gp, double sr, double si) {
-  double cfix, g[5];
+__device__ __forceinline__ PhaseF phase_factors(const Tables* T, const double* fl, double cblk,
+                                                int lane, int wave, double gp, double sr,
+                                                double si) {
+  double cfix, g[6];
   thread_energy<PL>(T, fl, cblk, lane, wave, cfix, g);
-  float2 f0 = unit(gp * cfix);
-  f0 = cmul(f0, make_float2((float)sr, (float)si));
-  float2 fs[5];
+  PhaseF P;
+  P.f0 = cmul(unit(gp * cfix), make_float2((float)sr, (float)si));
 #pragma unroll
-  for (int s = 0; s < 5; ++s) fs[s] = unit(gp * g[s]);
+  for (int s = 0; s < 6; ++s) P.fs[s] = unit(gp * g[s]);
+  return P;
+}
+
+// Phase of one layer on the 64 register amplitudes: amplitude r is
+// multiplied by f0 * prod_{s in r} fs[s] * KF[r].
+__device__ __forceinline__ void apply_phase(float2 (&v)[64], const float2* KF, const PhaseF& P) {
 #pragma unroll
-  for (int r4 = 0; r4 < 2; ++r4) {
-    const float2 p4 = r4 ? cmul(f0, fs[4]) : f0;
+  for (int r5 = 0; r5 < 2; ++r5) {
+    const float2 p5 = r5 ? cmul(P.f0, P.fs[5]) : P.f0;
 #pragma unroll
-    for (int r3 = 0; r3 < 2; ++r3) {
-      const float2 p3 = r3 ? cmul(p4, fs[3]) : p4;
+    for (int r4 = 0; r4 < 2; ++r4) {
+      const float2 p4 = r4 ? cmul(p5, P.fs[4]) : p5;
 #pragma unroll
-      for (int r2 = 0; r2 < 2; ++r2) {
-        const float2 p2 = r2 ? cmul(p3, fs[2]) : p3;
+      for (int r3 = 0; r3 < 2; ++r3) {
+        const float2 p3 = r3 ? cmul(p4, P.fs[3]) : p4;
 #pragma unroll
-        for (int r1 = 0; r1 < 2; ++r1) {
-          const float2 p1 = r1 ? cmul(p2, fs[1]) : p2;
+        for (int r2 = 0; r2 < 2; ++r2) {
+          const float2 p2 = r2 ? cmul(p3, P.fs[2]) : p3;
 #pragma unroll
-          for (int r0 = 0; r0 < 2; ++r0) {
-            const float2 p0 = r0 ? cmul(p1, fs[0]) : p1;
-            const int r = r0 | (r1 << 1) | (r2 << 2) | (r3 << 3) | (r4 << 4);
-            v[r] = cmul(v[r], cmul(p0, KF[r]));
+          for (int r1 = 0; r1 < 2; ++r1) {
+            const float2 p1 = r1 ? cmul(p2, P.fs[1]) : p2;
+#pragma unroll
+            for (int r0 = 0; r0 < 2; ++r0) {
+              const float2 p0 = r0 ? cmul(p1, P.fs[0]) : p1;
+              const int r = r0 | (r1 << 1) | (r2 << 2) | (r3 << 3) | (r4 << 4) | (r5 << 5);
+              v[r] = cmul(v[r], cmul(p0, KF[r]));
+            }
+            __builtin_amdgcn_sched_barrier(0);
           }
         }
       }
@@ -389,63 +413,69 @@ __device__ __forceinline__ void apply_phase(float2 (&v)[32], const Tables* T, co
   }
 }
 
-// <C> and norm partial sums of the 32 register amplitudes, FP64.
-template <int PL>
-__device__ __forceinline__ void reduce_regs(const float2 (&v)[32], const Tables* T,
-                                            const double* fl, double cblk, int lane, int wave,
-                                            double& ae, double& an) {
-  double cfix, g[5];
-  thread_energy<PL>(T, fl, cblk, lane, wave, cfix, g);
+// <C> and norm partial sums of the 64 register amplitudes, FP64, from the
+// thread's cfix and fields g (thread_energy).
+__device__ __forceinline__ void reduce_regs(const float2 (&v)[64], const Tables* T, double cfix,
+                                            const double (&g)[6], double& ae, double& an) {
 #pragma unroll
-  for (int r = 0; r < 32; ++r) {
-    double c = cfix + T->Kr[r];
+  for (int hi = 0; hi < 8; ++hi) {  // register bits 3..5
+    double ch = cfix;
 #pragma unroll
-    for (int s = 0; s < 5; ++s)
-      if ((r >> s) & 1) c += g[s];
-    const double pz = (double)v[r].x * v[r].x + (double)v[r].y * v[r].y;
-    ae = fma(pz, c, ae);
-    an += pz;
+    for (int s = 3; s < 6; ++s)
+      if ((hi >> (s - 3)) & 1) ch += g[s];
+#pragma unroll
+    for (int lo = 0; lo < 8; ++lo) {  // register bits 0..2
+      const int r = (hi << 3) | lo;
+      double c = ch + T->Kr[r];
+#pragma unroll
+      for (int s = 0; s < 3; ++s)
+        if ((lo >> s) & 1) c += g[s];
+      const double pz = (double)v[r].x * v[r].x + (double)v[r].y * v[r].y;
+      ae = fma(pz, c, ae);
+      an += pz;
+    }
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
-// Global load/store of the register tile in layout L (pairs of amplitudes
-// differing in tile bit 0 move as one 16-byte access).
-// Rows rp in [RP0, RP0 + NRP) of the tile (register indices 2rp, 2rp + 1)
-// into dst[2 * (rp - RP0) + D0 ...].
-template <int L, int RP0, int NRP, int D0, int N>
-__device__ __forceinline__ void load_rows(float2 (&dst)[N], const float2* base, int lane,
-                                          int wave, int kind, int a) {
+// Global load/store of the register tile in layout L (the two amplitudes of a
+// register pair differ in tile bit 0 and move as one 16-byte access).
+template <int L>
+__device__ __forceinline__ void load_tile(float2 (&v)[64], const float2* base, int lane, int wave,
+                                          int kind, int a) {
   const uint64_t tb = dep14(thread_bits<L>(lane, wave), kind, a);
 #pragma unroll
-  for (int i = 0; i < NRP; ++i) {
-    const int rp = RP0 + i;
+  for (int rp = 0; rp < 32; ++rp) {
     const uint64_t o = tb + dep14(reg_off<L>(rp) << 1, kind, a);
     const float4 q = *reinterpret_cast<const float4*>(base + o);
-    dst[D0 + 2 * i] = make_float2(q.x, q.y);
-    dst[D0 + 2 * i + 1] = make_float2(q.z, q.w);
+    v[rp << 1] = make_float2(q.x, q.y);
+    v[(rp << 1) | 1] = make_float2(q.z, q.w);
   }
 }
 
+// sw: tile bit 0 is flipped (the register pair is stored in swapped order).
 template <int L>
-__device__ __forceinline__ void store_tile(const float2 (&v)[32], float2* base, int lane, int wave,
-                                           int kind, int a) {
+__device__ __forceinline__ void store_tile(const float2 (&v)[64], float2* base, int lane, int wave,
+                                           int kind, int a, bool sw) {
   const uint64_t tb = dep14(thread_bits<L>(lane, wave), kind, a);
 #pragma unroll
-  for (int rp = 0; rp < 16; ++rp) {
+  for (int rp = 0; rp < 32; ++rp) {
     const uint64_t o = tb + dep14(reg_off<L>(rp) << 1, kind, a);
-    const float2 u = v[rp << 1], w = v[(rp << 1) | 1];
+    const float2 e0 = v[rp << 1], e1 = v[(rp << 1) | 1];
+    const float2 u = sw ? e1 : e0, w = sw ? e0 : e1;
     *reinterpret_cast<float4*>(base + o) = make_float4(u.x, u.y, w.x, w.y);
   }
 }
 
 template <int L>
-__device__ __forceinline__ void store_probs(const float2 (&v)[32], float* base, int lane,
-                                            int wave, int kind, int a, float scale) {
+__device__ __forceinline__ void store_probs(const float2 (&v)[64], float* base, int lane,
+                                            int wave, int kind, int a, float scale, bool sw) {
   const uint64_t tb = dep14(thread_bits<L>(lane, wave), kind, a);
 #pragma unroll
-  for (int rp = 0; rp < 16; ++rp) {
+  for (int rp = 0; rp < 32; ++rp) {
     const uint64_t o = tb + dep14(reg_off<L>(rp) << 1, kind, a);
-    const float2 u = v[rp << 1], w = v[(rp << 1) | 1];
+    const float2 e0 = v[rp << 1], e1 = v[(rp << 1) | 1];
+    const float2 u = sw ? e1 : e0, w = sw ? e0 : e1;
     *reinterpret_cast<float2*>(base + o) =
         make_float2(scale * (u.x * u.x + u.y * u.y), scale * (w.x * w.x + w.y * w.y));
   }
@@ -462,194 +492,155 @@ __device__ __forceinline__ double bsum14(double x, double* red) {
   return s;
 }
 
-// Block bits of tile ti.
-template <int KIND>
-__device__ __forceinline__ uint64_t tile_base(uint64_t ti, int a) {
-  if (KIND == 1) return ti << 14;
-  const int gap = a - 4;
-  return ((ti & ((1ull << gap) - 1ull)) << 4) | ((ti >> gap) << (a + 10));
-}
+// Pass shapes (every pass of a register-tile plan is one of these):
+//   P_FIRST  initial state, phase, half-mixer PL -> LA, store (set 0)
+//   P_MID    load, lead half-mixer LA -> PL, phase, half-mixer PL -> LA, store
+//   P_LEAD   load, lead half-mixer LA -> PL, store (sets between the ends of a
+//            layer when there are more than two)
+//   P_LAST   load, lead half-mixer LA -> PL, <C>/norm partials and the
+//            optional probability and state outputs
+enum { P_FIRST = 0, P_MID = 1, P_LEAD = 2, P_LAST = 3 };
 
-// Per-tile context in LDS: fields of the block bits on the tile bits (fl),
-// couplings among tile bits (Wl), the energy of the block bits (returned),
-// and the phase tables of layout PL.
-template <int KIND, int PL>
-__device__ __forceinline__ double tile_context(const PassDesc& d, const double* Wsh, uint64_t zb, double* fl,
-                               double* Wl, double* tmp, Tables* T, int tid) {
-  const int n = d.n;
-  if (tid < 14) {
-    const int pi = (KIND == 1 || tid < 4) ? tid : d.a + tid - 4;
-    double f = Wsh[pi * n + pi];
-    for (int j = 0; j < n; ++j)
-      if ((zb >> j) & 1ull) f += Wsh[pi * n + j];
-    fl[tid] = f;
-  }
-  if (tid >= 64 && tid < 64 + 196) {
-    const int e = tid - 64, i = e / 14, j = e - 14 * i;
-    const int pi = (KIND == 1 || i < 4) ? i : d.a + i - 4;
-    const int pj = (KIND == 1 || j < 4) ? j : d.a + j - 4;
-    Wl[e] = (i == j) ? 0.0 : Wsh[pi * n + pj];
-  }
-  if (tid >= 320 && tid < 320 + n) {
-    const int i = tid - 320;
-    double t = 0.0;
-    if ((zb >> i) & 1ull) {
-      t = Wsh[i * n + i];
-      for (int j = 0; j < i; ++j)
-        if ((zb >> j) & 1ull) t += Wsh[i * n + j];
-    }
-    tmp[i] = t;
-  }
-  lds_barrier();
-  double cblk = 0.0;
-  for (int i = 0; i < n; ++i) cblk += tmp[i];
-  build_tables<PL>(T, fl, Wl, tid);
-  lds_barrier();
-  return cblk;
-}
-
-// One tile of a pass whose input tile `v` is already in registers (layout LA)
-// or, for the first pass, is generated here.  Layouts LA (load), LB, LC
-// (phase); the pass mixes tile bits [MIXLO, 14).
-template <int LA, int LB, int LC, int MIXLO>
-__device__ __forceinline__ void tile14(const F14Args& A, float2 (&v)[32], float2* buf,
-                                       Tables* T, float2* KF, const double* fl, double cblk,
-                                       int lane, int wave, uint64_t st, uint64_t ti, uint64_t zb,
-                                       const LayerCoef* cf) {
-  const PassDesc& d = A.d;
-  const int m = 14 - d.mixlo;
-  // pending mixer scalar at the start of the pass
-  double sr = 1.0, si = 0.0;
-  for (int i = 0; i < d.pend_n; ++i) half_scale(cf[d.pend_layer[i]], d.pend_m[i], sr, si);
-  const bool has_phase = d.ja <= d.jb;
-  int where = (d.flags & F_INIT) ? 2 : 0;  // 0: layout LA, 2: layout LC
-  if (d.lead >= 0) {  // lead half-mixer: LA -> LB -> LC
-    const LayerCoef& L = cf[d.lead];
-    const float t = (float)L.tb;
-    if (L.mode == 0) half_mixer<0, LA, LB, LC, MIXLO>(v, buf, lane, wave, t);
-    else half_mixer<1, LA, LB, LC, MIXLO>(v, buf, lane, wave, t);
-    half_scale(L, m, sr, si);
-    where = 2;
-  }
-  if (has_phase) {  // phase of layer jb, then its half-mixer LC -> LB -> LA
-    const LayerCoef& L = cf[d.jb];
-    if (threadIdx.x < 32) KF[threadIdx.x] = unit(L.gp * T->Kr[threadIdx.x]);
-    lds_barrier();
-    apply_phase<LC>(v, T, KF, fl, cblk, lane, wave, L.gp, sr, si);
-    sr = 1.0;
-    si = 0.0;
-    const float t = (float)L.tb;
-    if (L.mode == 0) half_mixer<0, LC, LB, LA, MIXLO>(v, buf, lane, wave, t);
-    else half_mixer<1, LC, LB, LA, MIXLO>(v, buf, lane, wave, t);
-    where = 0;
-  }
-  if (d.flags & F_REDUCE) {
-    // outputs of the final pass carry the pending scalar; it is in LC here
-    const float fr = (float)sr, fi = (float)si;
-    if (d.flags & F_PROBS) {
-      const float s2 = (float)(sr * sr + si * si);
-      store_probs<LC>(v, A.probs + (st << d.n) + zb, lane, wave, d.kind, d.a, s2);
-    }
-    if (d.flags & F_WRITE) {
-#pragma unroll
-      for (int r = 0; r < 32; ++r) v[r] = cmul(v[r], make_float2(fr, fi));
-      store_tile<LC>(v, A.out + st * A.stride + zb, lane, wave, d.kind, d.a);
-    }
-    double ae = 0.0, an = 0.0;
-    reduce_regs<LC>(v, T, fl, cblk, lane, wave, ae, an);
-    double* red = reinterpret_cast<double*>(KF);  // KF is unused in the last pass
-    const double s2 = (d.flags & F_WRITE) ? 1.0 : sr * sr + si * si;
-    const double se = bsum14(ae, red) * s2;
-    const double sn = bsum14(an, red) * s2;
-    if (threadIdx.x == 0) {
-      double* o = A.part + ((st << (d.n - 14)) + ti) * 2;
-      o[0] = se;
-      o[1] = sn;
-    }
-  } else if (d.flags & F_WRITE) {
-    float2* g = A.out + st * A.stride + zb;
-    if (where == 0) store_tile<LA>(v, g, lane, wave, d.kind, d.a);
-    else store_tile<LC>(v, g, lane, wave, d.kind, d.a);
-  }
-}
-
-// Persistent kernel: work-group w processes tiles w, w + G, w + 2G, ... of
-// all states (tile index = state * 2^(n-14) + tile); while it computes one
-// tile, the next tile's loads are in flight into a second register buffer.
-template <int KIND, int MIXLO>
-__global__ void __launch_bounds__(NT14) fwd14_kernel(F14Args A) {
-  constexpr int LB = KIND == 1 ? 1 : 3, LC = KIND == 1 ? 2 : 4;
-  __shared__ float2 buf[PHYS];
+// One tile of one pass per work-group (tile index = state * 2^(n-14) + tile
+// of the state).  Layout 0 is the load/store layout and PL the phase layout;
+// the pass mixes tile bits [MIXLO, 14).  One straight-line body per pass
+// shape keeps the 128 registers of the tile in place from load to store.
+template <int KIND, int MIXLO, int PT>
+__global__ void __launch_bounds__(NT14) __attribute__((amdgpu_waves_per_eu(2)))
+fwd14_kernel(F14Args A) {
+  constexpr int LA = 0, PL = KIND == 1 ? 1 : 2;
+  constexpr bool LEAD = PT != P_FIRST, PHASE = PT == P_FIRST || PT == P_MID;
+  __shared__ float2 buf[HALF];
   __shared__ Tables T;
   __shared__ double fl[14];
   __shared__ double Wl[14 * 14];
   __shared__ double tmp[40];
-  __shared__ float2 KF[32];
-  __shared__ double Wsh[34 * 34];  // the current problem's folded Q
-  __shared__ LayerCoef Csh[64];    // the current state's layer coefficients
+  __shared__ float2 KF[64];
+  __shared__ LayerCoef cf[64];
   const PassDesc& d = A.d;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nlog = d.n - 14;
-  const uint64_t total = (uint64_t)A.nstates << nlog;
-  const uint64_t tmask = (1ull << nlog) - 1ull;
-  const bool init = (d.flags & F_INIT) != 0;
-  // rows 0..7 of the next tile (half of it) are prefetched into registers
-  // while the current tile is computed; rows 8..15 are loaded at tile start
-  float2 nxt[16];
-  uint64_t tile = blockIdx.x;
-  int64_t prob = -1, cst = -1;
-  auto tile_ptr = [&](uint64_t t) {
-    return A.in + (t >> nlog) * A.stride + tile_base<KIND>(t & tmask, d.a);
-  };
-  if (!init && tile < total) load_rows<0, 0, 8, 0>(nxt, tile_ptr(tile), lane, wave, d.kind, d.a);
-  for (; tile < total; tile += gridDim.x) {
-    const uint64_t st = tile >> nlog, ti = tile & tmask;
-    const uint64_t zb = tile_base<KIND>(ti, d.a);
-    const int64_t pr = (int64_t)(st / A.S);
-    if (pr != prob) {  // stage W in LDS (rare: once per problem)
-      const double* W = A.W + (size_t)pr * d.n * d.n;
-      for (int e = tid; e < d.n * d.n; e += NT14) Wsh[e] = W[e];
-      prob = pr;
-      __syncthreads();
-    }
-    if ((int64_t)st != cst) {  // stage the state's layer coefficients in LDS
-      const LayerCoef* c = A.coef + st * A.p;
-      for (int e = tid; e < A.p; e += NT14) Csh[e] = c[e];
-      cst = (int64_t)st;
-      __syncthreads();
-    }
-    const double cblk = tile_context<KIND, LC>(d, Wsh, zb, fl, Wl, tmp, &T, tid);
-    float2 v[32];
-    if (init) {
-      const float amp = (float)exp2(-0.5 * (double)d.n);
-#pragma unroll
-      for (int r = 0; r < 32; ++r) v[r] = make_float2(amp, 0.0f);
-    } else {
-      load_rows<0, 8, 8, 16>(v, tile_ptr(tile), lane, wave, d.kind, d.a);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) v[r] = nxt[r];
-      // Rows 0..7 of the next tile (the last tile re-reads itself, so the
-      // loads are unconditional and every wait on this tile's loads has a
-      // fixed count that leaves the prefetch in flight).
-      const uint64_t nx = tile + gridDim.x < total ? tile + gridDim.x : tile;
-      __builtin_amdgcn_sched_barrier(0);
-      load_rows<0, 0, 8, 0>(nxt, tile_ptr(nx), lane, wave, d.kind, d.a);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    tile14<0, LB, LC, MIXLO>(A, v, buf, &T, KF, fl, cblk, lane, wave, st, ti, zb, Csh);
-    lds_barrier();  // the next tile rewrites the LDS context
+  const int n = d.n, nlog = n - 14;
+  const uint64_t tile = blockIdx.x;
+  const uint64_t st = tile >> nlog, ti = tile & ((1ull << nlog) - 1ull);
+  uint64_t zb;
+  if (KIND == 1) {
+    zb = ti << 14;
+  } else {
+    const int gap = d.a - 4;
+    zb = ((ti & ((1ull << gap) - 1ull)) << 4) | ((ti >> gap) << (d.a + 10));
   }
-}
+  // Tile context: block fields on the tile bits, couplings among the tile
+  // bits, the energy of the block bits, the state's layer coefficients.
+  // With tile bit 0 flipped after the lead half-mixer (cot form on set 0),
+  // the tile-local energy is that of z ^ 1: the field and couplings of bit 0
+  // change sign, the other fields gain their coupling to bit 0, and the
+  // constant gains the old field of bit 0.
+  const double* W = A.W + (size_t)(st / A.S) * n * n;
+  const bool f0 = KIND == 1 && LEAD && A.coef[st * A.p + d.lead].mode != 0;
+  if (tid < 14) {
+    const int pi = (KIND == 1 || tid < 4) ? tid : d.a + tid - 4;
+    double f = W[pi * n + pi];
+    for (int j = 0; j < n; ++j)
+      if ((zb >> j) & 1ull) f += W[pi * n + j];
+    if (f0) f = tid == 0 ? -f : f + W[pi * n];
+    fl[tid] = f;
+  } else if (tid >= 64 && tid <= 64 + n) {
+    const int i = tid - 64;
+    double t = 0.0;
+    if (i == n) {  // old field of bit 0 (kind 1: tile bit 0 is qubit 0)
+      if (f0) {
+        t = W[0];
+        for (int j = 0; j < n; ++j)
+          if ((zb >> j) & 1ull) t += W[j];
+      }
+    } else if ((zb >> i) & 1ull) {
+      t = W[i * n + i];
+      for (int j = 0; j < i; ++j)
+        if ((zb >> j) & 1ull) t += W[i * n + j];
+    }
+    tmp[i] = t;
+  } else if (tid >= 128 && tid < 128 + A.p) {
+    cf[tid - 128] = A.coef[st * A.p + (tid - 128)];
+  }
+  if (tid < 196) {
+    const int i = tid / 14, j = tid - 14 * i;
+    const int pi = (KIND == 1 || i < 4) ? i : d.a + i - 4;
+    const int pj = (KIND == 1 || j < 4) ? j : d.a + j - 4;
+    const double w = (i == j) ? 0.0 : W[pi * n + pj];
+    Wl[tid] = (f0 && (i == 0) != (j == 0)) ? -w : w;
+  }
+  lds_barrier();
+  double cblk = 0.0;
+  for (int i = 0; i <= n; ++i) cblk += tmp[i];
+  if (PT != P_LEAD)
+    for (int e = tid; e < NTAB; e += NT14) table_entry<PL>(&T, fl, Wl, e);
+  if (PHASE && tid < 64) {
+    const LayerCoef& L = cf[d.jb];
+    // Kr of this thread's entry, computed here rather than read back
+    double k = 0.0;
+    for (int i = 0; i < 6; ++i)
+      if ((tid >> i) & 1)
+        for (int j = 0; j < i; ++j)
+          if ((tid >> j) & 1) k += Wl[reg_bit(PL, i) * 14 + reg_bit(PL, j)];
+    KF[tid] = unit(L.gp * k);
+  }
+  lds_barrier();
 
-int cu_count() {
-  static int n = [] {
-    int dev = 0, c = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 256;
-    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      return 256;
-    return c > 0 ? c : 256;
-  }();
-  return n;
+  // pending mixer scalar (at the phase, or at the outputs of the last pass)
+  double sr = 1.0, si = 0.0;
+  for (int i = 0; i < d.pend_n; ++i) half_scale(cf[d.pend_layer[i]], d.pend_m[i], sr, si);
+  if (LEAD) half_scale(cf[d.lead], 14 - MIXLO, sr, si);
+  // per-thread phase factors, or energies for <C>, before the tile arrives
+  PhaseF P;
+  double cfix = 0.0, g[6];
+  if (PHASE) P = phase_factors<PL>(&T, fl, cblk, lane, wave, cf[d.jb].gp, sr, si);
+  if (PT == P_LAST) thread_energy<PL>(&T, fl, cblk, lane, wave, cfix, g);
+  float2 v[64];
+  if (PT == P_FIRST) {
+    const float amp = (float)exp2(-0.5 * (double)n);
+#pragma unroll
+    for (int r = 0; r < 64; ++r) v[r] = make_float2(amp, 0.0f);
+  } else {
+    load_tile<LA>(v, A.in + st * A.stride + zb, lane, wave, KIND, d.a);
+  }
+  bool sw = f0;  // tile bit 0 is flipped
+  if (LEAD) {
+    const LayerCoef& L = cf[d.lead];
+    half_mixer<LA, PL, MIXLO>(v, buf, lane, wave, mix_t<MIXLO>(L), mix_fx<MIXLO>(L));
+  }
+  if (PHASE) {
+    const LayerCoef& L = cf[d.jb];
+    apply_phase(v, KF, P);
+    half_mixer<PL, LA, MIXLO>(v, buf, lane, wave, mix_t<MIXLO>(L), mix_fx<MIXLO>(L));
+    if (KIND == 1 && L.mode != 0) sw = !sw;
+    store_tile<LA>(v, A.out + st * A.stride + zb, lane, wave, KIND, d.a, sw);
+  } else if (PT == P_LEAD) {
+    store_tile<PL>(v, A.out + st * A.stride + zb, lane, wave, KIND, d.a, sw);
+  } else {
+    // outputs of the final pass carry the pending scalar
+    if (d.flags & F_PROBS) {
+      const float s2 = (float)(sr * sr + si * si);
+      store_probs<PL>(v, A.probs + (st << n) + zb, lane, wave, KIND, d.a, s2, sw);
+    }
+    if (d.flags & F_WRITE) {
+      const float2 sc = make_float2((float)sr, (float)si);
+#pragma unroll
+      for (int r = 0; r < 64; ++r) v[r] = cmul(v[r], sc);
+      store_tile<PL>(v, A.out + st * A.stride + zb, lane, wave, KIND, d.a, sw);
+      sr = 1.0;
+      si = 0.0;
+    }
+    double ae = 0.0, an = 0.0;
+    reduce_regs(v, &T, cfix, g, ae, an);
+    const double s2 = sr * sr + si * si;
+    const double se = bsum14(ae, tmp) * s2;
+    const double sn = bsum14(an, tmp) * s2;
+    if (tid == 0) {
+      double* o = A.part + tile * 2;
+      o[0] = se;
+      o[1] = sn;
+    }
+  }
 }
 
 }  // namespace
@@ -658,11 +649,24 @@ hipError_t launch_fwd14_pass(const PassDesc& d, int nstates, int S, int p,
                              const void* in, void* out, uint64_t state_stride,
                              const double* W, const LayerCoef* coef,
                              double* part, void* probs, hipStream_t stream) {
+  if (d.n < 15 || d.n > 34 || p < 1 || p > 64 || nstates < 1 || S < 1)
+    return hipErrorInvalidValue;
+  const bool phase = d.ja <= d.jb;
+  if (phase && (d.ja != d.jb || d.jb < 0 || d.jb >= p)) return hipErrorInvalidValue;
+  if (d.lead >= p) return hipErrorInvalidValue;
+  int pt;
+  if (d.flags & F_INIT) pt = (d.lead < 0 && phase && d.kind == 1 && (d.flags & F_WRITE) &&
+                              !(d.flags & F_REDUCE)) ? P_FIRST : -1;
+  else if (d.lead < 0) pt = -1;
+  else if (d.flags & F_REDUCE) pt = phase ? -1 : P_LAST;
+  else if (!(d.flags & F_WRITE)) pt = -1;
+  else pt = phase ? P_MID : P_LEAD;
+  if (pt < 0 || (d.kind == 1 && pt == P_LEAD)) return hipErrorInvalidValue;
+  if (d.kind == 1 ? d.mixlo != 0 : (d.mixlo < 4 || d.mixlo > 13)) return hipErrorInvalidValue;
   F14Args A;
   A.d = d;
   A.S = S;
   A.p = p;
-  A.nstates = nstates;
   A.in = reinterpret_cast<const float2*>(in);
   A.out = reinterpret_cast<float2*>(out);
   A.stride = state_stride;
@@ -671,26 +675,36 @@ hipError_t launch_fwd14_pass(const PassDesc& d, int nstates, int S, int p,
   A.part = part;
   A.probs = reinterpret_cast<float*>(probs);
   const uint64_t total = (uint64_t)nstates << (d.n - 14);
-  const uint64_t g = (uint64_t)cu_count();  // one 512-thread work-group per CU
-  const dim3 grid((unsigned)(total < g ? total : g)), blk(NT14);
-#define DQ_K(K, M) hipLaunchKernelGGL((fwd14_kernel<K, M>), grid, blk, 0, stream, A)
+  if (total > 0xFFFFFFFFull) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)total), blk(NT14);
+#define DQ_K(K, M, T) hipLaunchKernelGGL((fwd14_kernel<K, M, T>), grid, blk, 0, stream, A)
+#define DQ_PT(K, M)                         \
+  switch (pt) {                             \
+    case P_MID: DQ_K(K, M, P_MID); break;   \
+    case P_LEAD: DQ_K(K, M, P_LEAD); break; \
+    default: DQ_K(K, M, P_LAST); break;     \
+  }
   if (d.kind == 1) {
-    DQ_K(1, 0);
+    switch (pt) {
+      case P_FIRST: DQ_K(1, 0, P_FIRST); break;
+      case P_MID: DQ_K(1, 0, P_MID); break;
+      default: DQ_K(1, 0, P_LAST); break;
+    }
   } else {
     switch (d.mixlo) {
-      case 4: DQ_K(2, 4); break;
-      case 5: DQ_K(2, 5); break;
-      case 6: DQ_K(2, 6); break;
-      case 7: DQ_K(2, 7); break;
-      case 8: DQ_K(2, 8); break;
-      case 9: DQ_K(2, 9); break;
-      case 10: DQ_K(2, 10); break;
-      case 11: DQ_K(2, 11); break;
-      case 12: DQ_K(2, 12); break;
-      case 13: DQ_K(2, 13); break;
-      default: return hipErrorInvalidValue;
+      case 4: DQ_PT(2, 4); break;
+      case 5: DQ_PT(2, 5); break;
+      case 6: DQ_PT(2, 6); break;
+      case 7: DQ_PT(2, 7); break;
+      case 8: DQ_PT(2, 8); break;
+      case 9: DQ_PT(2, 9); break;
+      case 10: DQ_PT(2, 10); break;
+      case 11: DQ_PT(2, 11); break;
+      case 12: DQ_PT(2, 12); break;
+      default: DQ_PT(2, 13); break;
     }
   }
+#undef DQ_PT
 #undef DQ_K
   return hipGetLastError();
 }
