@@ -6,24 +6,27 @@
 // but the 2^14-amplitude tile lives in registers: 256 threads (4 waves) x 64
 // amplitudes, i.e. 6 "register" tile bits per thread, 6 lane bits and 2 wave
 // bits.  LDS only moves tile bits between registers and lanes/waves
-// (transposes), one 64 KiB half at a time (halves split on tile bit 0, a
-// register bit in every layout), so a work-group needs about 73 KiB and two
-// share a CU: while one waits at a barrier or on memory, the other computes.
+// (transposes), one half at a time (halves split on tile bit 0, a register
+// bit in every layout), so a work-group needs about 77 KiB and two share a
+// CU: while one waits at a barrier or on memory, the other computes.
 //
-// A half-mixer (the mixer of one layer on the pass's qubit set) visits two
-// layouts: in each, the butterflies of its register bits run in registers and
-// those of lane bits 0 and 1 run across lanes with DPP quad permutes, so 6 + 2
-// tile bits can be mixed per layout and one transpose per half-mixer does.
+// A half-mixer (the mixer of one layer on the pass's qubit set) runs its
+// butterflies on register bits only: in each of two layouts, the tile's six
+// register bits, plus lane bits 4 and 5 brought into registers by the gfx950
+// lane-swap instructions (v_permlane16_swap / v_permlane32_swap exchange a
+// register-pair bit with lane bit 4 / 5 at one instruction per two
+// registers), with one LDS transpose between the layouts.
+//
 // The butterfly is the tan/cot form (two FMAs per component); the scalar c^m
-// or (i s)^m of each half-mixer is left pending and folded into the next phase
-// multiply, or into the outputs of the last pass.  Both forms run the same
-// arithmetic, (a0, a1) -> (a0 + i t a1, a1 + i t a0): cos b I + i sin b X
+// or (i s)^m of each half-mixer is left pending and folded into the next
+// phase multiply, or into the outputs of the last pass.  Both forms run the
+// same arithmetic, (a0, a1) -> (a0 + i t a1, a1 + i t a0): cos b I + i sin b X
 // equals i sin b X (I + i t X) with t = -cot b, and the trailing X on every
 // mixed qubit commutes with the whole half-mixer, so it becomes a relabelling
 // of the tile.  The transpose inside the half-mixer applies it to tile bits
-// 1..13 by XORing its LDS write address; a flip of tile bit 0 (only set 0
-// mixes it) stays pending: the phase tables are built for the flipped bit and
-// the stores swap the two amplitudes of each register pair.
+// 1..13 through its write and read base addresses; a flip of tile bit 0 (only
+// set 0 mixes it) stays pending: the phase tables are built for the flipped
+// bit and the stores swap the two amplitudes of each register pair.
 //
 // Phase: C(z) = cfix(thread) + sum_s r_s g_s(thread) + K(r) over the thread's
 // 6 register bits r.  cfix and g come from per-tile FP64 tables in LDS (lane
@@ -46,31 +49,46 @@ constexpr int HALF = 1 << 13;  // amplitudes per LDS half
 
 // Layouts: the tile bit held by register slots 0..5, lane slots 0..5 and wave
 // slots 0..1.  Register slot 0 is tile bit 0 everywhere (the transpose pivot).
-//   0: A   load/store layout (lane slots = tile bits 1..6: 1 KiB runs)
-//   1: B   phase layout of qubit set 0 (A and B together mix tile bits 0..13)
-//   2: B'  phase layout of the other sets (A and B' together mix bits 4..13)
+//   L_A   load/store layout: lane slots are tile bits 1..6 (1 KiB runs)
+//   L_A1  L_A with register slots 4, 5 swapped with lane slots 4, 5
+//   L_B   set 0: the bits L_A1 leaves unmixed (1..4, 12) in registers
+//   L_B1  L_B with register slot 5 swapped with lane slot 4 (bit 13 in
+//         registers); phase layout of set 0
+//   L_B2  other sets: bits 4, 5, 6, 12, 13 in registers; phase layout
+// Set 0 mixes in A, A1 | transpose | B, B1 and back in reverse; the other
+// sets in A | transpose | B2 and back.  In every layout that meets LDS (A, A1,
+// B, B2) lane slots 0..3 are half-index bits whose swizzled low nibbles are
+// independent, so a 16-lane group of an LDS access hits 16 distinct banks.
+enum { L_A = 0, L_A1 = 1, L_B = 2, L_B1 = 3, L_B2 = 4 };
 __host__ __device__ constexpr int reg_bit(int L, int s) {
-  constexpr int t[3][6] = {{0, 7, 8, 9, 10, 11}, {0, 7, 3, 4, 5, 6}, {0, 7, 4, 5, 6, 12}};
+  constexpr int t[5][6] = {{0, 7, 8, 9, 10, 11},
+                           {0, 7, 8, 9, 5, 6},
+                           {0, 1, 2, 3, 4, 12},
+                           {0, 1, 2, 3, 4, 13},
+                           {0, 4, 12, 13, 5, 6}};
   return t[L][s];
 }
 __host__ __device__ constexpr int lane_bit(int L, int s) {
-  constexpr int t[3][6] = {{1, 2, 3, 4, 5, 6}, {12, 13, 1, 2, 8, 9}, {13, 1, 2, 3, 8, 9}};
+  constexpr int t[5][6] = {{1, 2, 3, 4, 5, 6},
+                           {1, 2, 3, 4, 10, 11},
+                           {5, 6, 7, 8, 13, 9},
+                           {5, 6, 7, 8, 12, 9},
+                           {1, 2, 3, 8, 7, 9}};
   return t[L][s];
 }
 __host__ __device__ constexpr int wave_bit(int L, int s) {
-  constexpr int t[3][2] = {{12, 13}, {10, 11}, {10, 11}};
+  constexpr int t[5][2] = {{12, 13}, {12, 13}, {10, 11}, {10, 11}, {10, 11}};
   return t[L][s];
 }
 
-// XOR swizzle of a half index h (tile index without bit 0): the low 4 bits
-// (an 8-byte bank within a 128-byte row) are XORed with a linear function of
-// the higher bits chosen so that in every layout lane slots 0..3 land on 4
-// independent bank bits, and each 16-lane group of an access hits 16 banks.
-// Linear over GF(2): swz(a ^ b) = swz(a) ^ swz(b).
-__host__ __device__ constexpr uint32_t swz(uint32_t h) {
-  return h ^ (((h >> 4) & 15u) ^ ((h >> 8) & 7u) ^ (((h >> 11) & 1u) << 2) ^
-              (((h >> 12) & 1u) << 3));
-}
+// Padded LDS slot of a half index h (tile index without bit 0): one pad slot
+// per 16.  Additive over disjoint bit sets (so a register's slot is the
+// thread's base plus an immediate offset), and half-index bit j moves the
+// slot by 2^j (j < 4) or 2^(j-4) (4 <= j < 8) modulo 16: lane slots 0..3
+// of every LDS layout take one bit from each class, so a 16-lane group of an
+// access hits 16 distinct 8-byte banks.
+__host__ __device__ constexpr uint32_t phys(uint32_t h) { return h + (h >> 4); }
+constexpr int PHYS = HALF + (HALF >> 4);
 
 // Half index of register index r' (register slots 1..5).
 template <int L>
@@ -107,48 +125,51 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Move the tile from layout X to layout Y through LDS, one half at a time;
-// fx (a swizzled half-index mask) relabels the tile: the amplitude at tile
-// index l moves to l ^ (fx's tile bits).
-template <int X, int Y>
+// Tile bits of layout L held by lanes and waves.
+template <int L>
+__host__ __device__ constexpr uint32_t thread_mask() {
+  uint32_t m = 0;
+  for (int s = 0; s < 6; ++s) m |= 1u << lane_bit(L, s);
+  for (int s = 0; s < 2; ++s) m |= 1u << wave_bit(L, s);
+  return m;
+}
+// Move the tile from layout X to layout Y through LDS, one half at a time.
+// With flip, the tile is relabelled on the way: the amplitude at tile index l
+// moves to l ^ M, M = the mixed tile bits [MIXLO, 14) without bit 0.  X and Y
+// share only tile bit 0 among their register bits, so every bit of M is a
+// lane or wave bit of X (flipped in the write base) or of Y (flipped in the
+// read base): the relabelling costs nothing per access.
+template <int X, int Y, int MIXLO>
 __device__ __forceinline__ void transpose(float2 (&v)[64], float2* buf, int lane, int wave,
-                                          uint32_t fx) {
-  const uint32_t bx = swz(thread_bits<X>(lane, wave) >> 1) ^ fx;
-  const uint32_t by = swz(thread_bits<Y>(lane, wave) >> 1);
+                                          bool flip) {
+  constexpr uint32_t M = ((0x3FFFu >> MIXLO) << MIXLO) & ~1u;
+  constexpr uint32_t M1 = M & thread_mask<X>(), M2 = M & ~M1;
+  static_assert((M2 & ~thread_mask<Y>()) == 0, "a mixed bit is a register bit of both layouts");
+  const uint32_t tx = thread_bits<X>(lane, wave) ^ (flip ? M1 : 0u);
+  const uint32_t ty = thread_bits<Y>(lane, wave) ^ (flip ? M2 : 0u);
+  float2* const bx = buf + phys(tx >> 1);
+  float2* const by = buf + phys(ty >> 1);
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
 #pragma unroll
-    for (int rp = 0; rp < 32; ++rp) buf[bx ^ swz(reg_off<X>(rp))] = v[(rp << 1) | h];
+    for (int q = 0; q < 32; ++q) bx[phys(reg_off<X>(q))] = v[(q << 1) | h];
     lds_barrier();
 #pragma unroll
-    for (int rp = 0; rp < 32; ++rp) v[(rp << 1) | h] = buf[by ^ swz(reg_off<Y>(rp))];
+    for (int q = 0; q < 32; ++q) v[(q << 1) | h] = by[phys(reg_off<Y>(q))];
     lds_barrier();
   }
 }
 
-__device__ __forceinline__ float dpp_x1(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x),
-                                                            0xB1, 0xF, 0xF, true));
-}
-__device__ __forceinline__ float dpp_x2(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x),
-                                                            0x4E, 0xF, 0xF, true));
-}
-
-// Tile bits a layout's register slots and DPP lane slots touch.
+// Register slots (bit s = slot s) that a round in layout L mixes: its tile
+// bits not mixed earlier in the same half-mixer (DONE) and at or above the
+// pass's first mixed bit.  Compile-time, so a round has no data-dependent
+// control flow.
 template <int L>
-__host__ __device__ constexpr uint32_t layout_mixable() {
+__host__ __device__ constexpr uint32_t reg_bits_of() {
   uint32_t m = 0;
   for (int s = 0; s < 6; ++s) m |= 1u << reg_bit(L, s);
-  m |= 1u << lane_bit(L, 0);
-  m |= 1u << lane_bit(L, 1);
   return m;
 }
-
-// Register slots (bit s = slot s) and DPP lane slots (bit 0 = lane bit 0,
-// bit 1 = lane bit 1) that a round in layout L mixes: its tile bits not mixed
-// earlier in the same half-mixer (DONE) and at or above the pass's first
-// mixed bit.  All compile-time, so a round has no data-dependent control flow.
 template <int L, uint32_t DONE, int MIXLO>
 __host__ __device__ constexpr unsigned reg_mask() {
   unsigned m = 0;
@@ -158,18 +179,9 @@ __host__ __device__ constexpr unsigned reg_mask() {
   }
   return m;
 }
-template <int L, uint32_t DONE, int MIXLO>
-__host__ __device__ constexpr unsigned dpp_mask() {
-  unsigned m = 0;
-  for (int s = 0; s < 2; ++s) {
-    const int b = lane_bit(L, s);
-    if (!((DONE >> b) & 1u) && b >= MIXLO) m |= 1u << s;
-  }
-  return m;
-}
 
-// (a0, a1) -> (a0 + i t a1, a1 + i t a0) on every selected bit.
-template <unsigned RM, unsigned DM>
+// (a0, a1) -> (a0 + i t a1, a1 + i t a0) on every register slot in RM.
+template <unsigned RM>
 __device__ __forceinline__ void mix_round(float2 (&v)[64], float t) {
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
@@ -189,53 +201,117 @@ __device__ __forceinline__ void mix_round(float2 (&v)[64], float t) {
       if ((r & 15) == 14 || (r & 15) == 15) __builtin_amdgcn_sched_barrier(0);
     }
   }
+}
+
+// Exchange register slot SR with lane slot SL (4 or 5) for the whole tile.
+template <int SR, int SL>
+__device__ __forceinline__ void swap_slot(float2 (&v)[64]) {
+  static_assert(SL == 4 || SL == 5, "lane slots 4 and 5 only");
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    if (!((DM >> s) & 1u)) continue;
-#pragma unroll
-    for (int r = 0; r < 64; ++r) {
-      const float x = v[r].x, y = v[r].y;
-      const float xp = s == 0 ? dpp_x1(x) : dpp_x2(x);
-      const float yp = s == 0 ? dpp_x1(y) : dpp_x2(y);
-      v[r].x = fmaf(-t, yp, x);
-      v[r].y = fmaf(t, xp, y);
-      // keep the DPP temporaries of only a few amplitudes live at a time
-      if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+  for (int r = 0; r < 64; ++r) {
+    if ((r >> SR) & 1) continue;
+    float2& a0 = v[r];
+    float2& a1 = v[r | (1 << SR)];
+    const unsigned x0 = __builtin_bit_cast(unsigned, a0.x);
+    const unsigned x1 = __builtin_bit_cast(unsigned, a1.x);
+    const unsigned y0 = __builtin_bit_cast(unsigned, a0.y);
+    const unsigned y1 = __builtin_bit_cast(unsigned, a1.y);
+    unsigned nx0, nx1, ny0, ny1;
+    if (SL == 5) {
+      const auto px = __builtin_amdgcn_permlane32_swap(x0, x1, false, false);
+      const auto py = __builtin_amdgcn_permlane32_swap(y0, y1, false, false);
+      nx0 = px[0], nx1 = px[1], ny0 = py[0], ny1 = py[1];
+    } else {
+      const auto px = __builtin_amdgcn_permlane16_swap(x0, x1, false, false);
+      const auto py = __builtin_amdgcn_permlane16_swap(y0, y1, false, false);
+      nx0 = px[0], nx1 = px[1], ny0 = py[0], ny1 = py[1];
     }
+    a0 = make_float2(__builtin_bit_cast(float, nx0), __builtin_bit_cast(float, ny0));
+    a1 = make_float2(__builtin_bit_cast(float, nx1), __builtin_bit_cast(float, ny1));
   }
 }
 
-// One half-mixer: a round in layout X, a transpose X -> Y (with the
-// relabelling fx), a round in Y.
-template <int X, int Y, int MIXLO>
-__device__ __forceinline__ void half_mixer(float2 (&v)[64], float2* buf, int lane, int wave,
-                                           float t, uint32_t fx) {
-  constexpr uint32_t D1 = layout_mixable<X>();
-  mix_round<reg_mask<X, 0, MIXLO>(), dpp_mask<X, 0, MIXLO>()>(v, t);
-  transpose<X, Y>(v, buf, lane, wave, fx);
-  mix_round<reg_mask<Y, D1, MIXLO>(), dpp_mask<Y, D1, MIXLO>()>(v, t);
+// Lead half-mixer: from the load layout L_A to the phase layout; trail
+// half-mixer: back.  flip (cot form) relabels the tile inside the transpose.
+template <int KIND, int MIXLO>
+__device__ __forceinline__ void lead_mixer(float2 (&v)[64], float2* buf, int lane, int wave,
+                                           float t, bool flip) {
+  if constexpr (KIND == 1) {
+    constexpr uint32_t D1 = reg_bits_of<L_A>();
+    constexpr uint32_t D2 = D1 | reg_bits_of<L_A1>();
+    constexpr uint32_t D3 = D2 | reg_bits_of<L_B>();
+    mix_round<reg_mask<L_A, 0, MIXLO>()>(v, t);
+    swap_slot<4, 4>(v);
+    swap_slot<5, 5>(v);
+    mix_round<reg_mask<L_A1, D1, MIXLO>()>(v, t);
+    transpose<L_A1, L_B, MIXLO>(v, buf, lane, wave, flip);
+    mix_round<reg_mask<L_B, D2, MIXLO>()>(v, t);
+    swap_slot<5, 4>(v);
+    mix_round<reg_mask<L_B1, D3, MIXLO>()>(v, t);
+  } else {
+    constexpr uint32_t D1 = reg_bits_of<L_A>();
+    mix_round<reg_mask<L_A, 0, MIXLO>()>(v, t);
+    transpose<L_A, L_B2, MIXLO>(v, buf, lane, wave, flip);
+    mix_round<reg_mask<L_B2, D1, MIXLO>()>(v, t);
+  }
+}
+template <int KIND, int MIXLO>
+__device__ __forceinline__ void trail_mixer(float2 (&v)[64], float2* buf, int lane, int wave,
+                                            float t, bool flip) {
+  if constexpr (KIND == 1) {
+    constexpr uint32_t D1 = reg_bits_of<L_B1>();
+    constexpr uint32_t D2 = D1 | reg_bits_of<L_B>();
+    constexpr uint32_t D3 = D2 | reg_bits_of<L_A1>();
+    mix_round<reg_mask<L_B1, 0, MIXLO>()>(v, t);
+    swap_slot<5, 4>(v);
+    mix_round<reg_mask<L_B, D1, MIXLO>()>(v, t);
+    transpose<L_B, L_A1, MIXLO>(v, buf, lane, wave, flip);
+    mix_round<reg_mask<L_A1, D2, MIXLO>()>(v, t);
+    swap_slot<4, 4>(v);
+    swap_slot<5, 5>(v);
+    mix_round<reg_mask<L_A, D3, MIXLO>()>(v, t);
+  } else {
+    constexpr uint32_t D1 = reg_bits_of<L_B2>();
+    mix_round<reg_mask<L_B2, 0, MIXLO>()>(v, t);
+    transpose<L_B2, L_A, MIXLO>(v, buf, lane, wave, flip);
+    mix_round<reg_mask<L_A, D1, MIXLO>()>(v, t);
+  }
 }
 
-// Arithmetic parameter of a half-mixer and its relabelling mask (the mixed
-// tile bits [MIXLO, 14) without bit 0, as a swizzled half index).
+// Arithmetic parameter of a half-mixer.
 template <int MIXLO>
 __device__ __forceinline__ float mix_t(const LayerCoef& L) {
   return L.mode == 0 ? (float)L.tb : -(float)L.tb;
-}
-template <int MIXLO>
-__device__ __forceinline__ uint32_t mix_fx(const LayerCoef& L) {
-  constexpr uint32_t mh = ((0x3FFFu >> MIXLO) << MIXLO) >> 1;
-  return L.mode == 0 ? 0u : swz(mh);
 }
 
 // Complex helpers.
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
 }
-__device__ __forceinline__ float2 unit(double rev) {  // e^{-i 2 pi rev}
-  const double t = rev - rint(rev);
-  float s, c;
-  sincospif(2.0f * (float)t, &s, &c);
+// e^{-i 2 pi rev}.  The angle is reduced in FP64 to t in [-1/2, 1/2], then to
+// an eighth of a turn: q = rint(4 t), theta = 2 pi (t - q / 4) in
+// [-pi/4, pi/4]; sin and cos of theta from their Taylor series through
+// theta^9 and theta^10 (truncation below 2e-9 there), rotated by q quarter
+// turns.
+__device__ __forceinline__ float2 unit(double rev) {
+  const float t = (float)(rev - rint(rev));
+  const float q = rintf(4.0f * t);
+  const float th = 6.28318530717958647692f * fmaf(-0.25f, q, t);
+  const float x = th * th;
+  const float sn =
+      th * fmaf(x, fmaf(x, fmaf(x, fmaf(x, 1.0f / 362880.0f, -1.0f / 5040.0f), 1.0f / 120.0f),
+                        -1.0f / 6.0f),
+                1.0f);
+  const float cs = fmaf(
+      x,
+      fmaf(x, fmaf(x, fmaf(x, fmaf(x, -1.0f / 3628800.0f, 1.0f / 40320.0f), -1.0f / 720.0f),
+                   1.0f / 24.0f),
+           -0.5f),
+      1.0f);
+  // (cos, sin) of theta + q pi / 2
+  const int k = (int)q & 3;
+  const float c = (k & 1) ? ((k & 2) ? sn : -sn) : ((k & 2) ? -cs : cs);
+  const float s = (k & 1) ? ((k & 2) ? -cs : cs) : ((k & 2) ? -sn : sn);
   return make_float2(c, -s);
 }
 
@@ -454,31 +530,43 @@ __device__ __forceinline__ void load_tile(float2 (&v)[64], const float2* base, i
 }
 
 // sw: tile bit 0 is flipped (the register pair is stored in swapped order).
+// sw: tile bit 0 is flipped (each register pair is stored in swapped
+// order).  The two orders are separate loops, not per-element selects.
+template <int L, bool SW>
+__device__ __forceinline__ void store_rows(const float2 (&v)[64], float2* base, uint64_t tb,
+                                           int kind, int a) {
+#pragma unroll
+  for (int rp = 0; rp < 32; ++rp) {
+    const uint64_t o = tb + dep14(reg_off<L>(rp) << 1, kind, a);
+    const float2 u = v[(rp << 1) | SW], w = v[(rp << 1) | !SW];
+    *reinterpret_cast<float4*>(base + o) = make_float4(u.x, u.y, w.x, w.y);
+  }
+}
 template <int L>
 __device__ __forceinline__ void store_tile(const float2 (&v)[64], float2* base, int lane, int wave,
                                            int kind, int a, bool sw) {
   const uint64_t tb = dep14(thread_bits<L>(lane, wave), kind, a);
+  if (sw) store_rows<L, true>(v, base, tb, kind, a);
+  else store_rows<L, false>(v, base, tb, kind, a);
+}
+
+template <int L, bool SW>
+__device__ __forceinline__ void store_prob_rows(const float2 (&v)[64], float* base, uint64_t tb,
+                                                int kind, int a, float scale) {
 #pragma unroll
   for (int rp = 0; rp < 32; ++rp) {
     const uint64_t o = tb + dep14(reg_off<L>(rp) << 1, kind, a);
-    const float2 e0 = v[rp << 1], e1 = v[(rp << 1) | 1];
-    const float2 u = sw ? e1 : e0, w = sw ? e0 : e1;
-    *reinterpret_cast<float4*>(base + o) = make_float4(u.x, u.y, w.x, w.y);
+    const float2 u = v[(rp << 1) | SW], w = v[(rp << 1) | !SW];
+    *reinterpret_cast<float2*>(base + o) =
+        make_float2(scale * (u.x * u.x + u.y * u.y), scale * (w.x * w.x + w.y * w.y));
   }
 }
-
 template <int L>
 __device__ __forceinline__ void store_probs(const float2 (&v)[64], float* base, int lane,
                                             int wave, int kind, int a, float scale, bool sw) {
   const uint64_t tb = dep14(thread_bits<L>(lane, wave), kind, a);
-#pragma unroll
-  for (int rp = 0; rp < 32; ++rp) {
-    const uint64_t o = tb + dep14(reg_off<L>(rp) << 1, kind, a);
-    const float2 e0 = v[rp << 1], e1 = v[(rp << 1) | 1];
-    const float2 u = sw ? e1 : e0, w = sw ? e0 : e1;
-    *reinterpret_cast<float2*>(base + o) =
-        make_float2(scale * (u.x * u.x + u.y * u.y), scale * (w.x * w.x + w.y * w.y));
-  }
+  if (sw) store_prob_rows<L, true>(v, base, tb, kind, a, scale);
+  else store_prob_rows<L, false>(v, base, tb, kind, a, scale);
 }
 
 __device__ __forceinline__ double bsum14(double x, double* red) {
@@ -508,9 +596,9 @@ enum { P_FIRST = 0, P_MID = 1, P_LEAD = 2, P_LAST = 3 };
 template <int KIND, int MIXLO, int PT>
 __global__ void __launch_bounds__(NT14) __attribute__((amdgpu_waves_per_eu(2)))
 fwd14_kernel(F14Args A) {
-  constexpr int LA = 0, PL = KIND == 1 ? 1 : 2;
+  constexpr int LA = L_A, PL = KIND == 1 ? L_B1 : L_B2;
   constexpr bool LEAD = PT != P_FIRST, PHASE = PT == P_FIRST || PT == P_MID;
-  __shared__ float2 buf[HALF];
+  __shared__ float2 buf[PHYS];
   __shared__ Tables T;
   __shared__ double fl[14];
   __shared__ double Wl[14 * 14];
@@ -529,44 +617,82 @@ fwd14_kernel(F14Args A) {
     const int gap = d.a - 4;
     zb = ((ti & ((1ull << gap) - 1ull)) << 4) | ((ti >> gap) << (d.a + 10));
   }
-  // Tile context: block fields on the tile bits, couplings among the tile
-  // bits, the energy of the block bits, the state's layer coefficients.
-  // With tile bit 0 flipped after the lead half-mixer (cot form on set 0),
-  // the tile-local energy is that of z ^ 1: the field and couplings of bit 0
-  // change sign, the other fields gain their coupling to bit 0, and the
-  // constant gains the old field of bit 0.
+  // The folded Q and the state's layer coefficients are read first, then the
+  // tile's own loads are issued, and Q and the coefficients are staged in LDS
+  // (the transpose buffer is idle until the first transpose) while the tile
+  // is in flight; the tile context is built from LDS meanwhile.
   const double* W = A.W + (size_t)(st / A.S) * n * n;
-  const bool f0 = KIND == 1 && LEAD && A.coef[st * A.p + d.lead].mode != 0;
+  const int nn = n * n;
+  double wr[(34 * 34 + NT14 - 1) / NT14];
+#pragma unroll
+  for (int k = 0; k < (34 * 34 + NT14 - 1) / NT14; ++k) {
+    const int e = tid + k * NT14;
+    wr[k] = e < nn ? W[e] : 0.0;
+  }
+  static_assert(sizeof(LayerCoef) == 40, "layer coefficients move as five doubles");
+  double cv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (tid < A.p) {
+    const double* c = reinterpret_cast<const double*>(A.coef + st * A.p + tid);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) cv[k] = c[k];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  float2 v[64];
+  if (PT == P_FIRST) {
+    const float amp = (float)exp2(-0.5 * (double)n);
+#pragma unroll
+    for (int r = 0; r < 64; ++r) v[r] = make_float2(amp, 0.0f);
+  } else {
+    load_tile<LA>(v, A.in + st * A.stride + zb, lane, wave, KIND, d.a);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  double* const Wsh = reinterpret_cast<double*>(buf);
+#pragma unroll
+  for (int k = 0; k < (34 * 34 + NT14 - 1) / NT14; ++k) {
+    const int e = tid + k * NT14;
+    if (e < nn) Wsh[e] = wr[k];
+  }
+  if (tid < A.p) {
+    double* c = reinterpret_cast<double*>(cf + tid);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) c[k] = cv[k];
+  }
+  lds_barrier();
+  // Tile context: block fields on the tile bits, couplings among the tile
+  // bits, the energy of the block bits.  With tile bit 0 flipped after the
+  // lead half-mixer (cot form on set 0), the tile-local energy is that of
+  // z ^ 1: the field and couplings of bit 0 change sign, the other fields
+  // gain their coupling to bit 0, and the constant gains the old field of
+  // bit 0.
+  const bool f0 = KIND == 1 && LEAD && cf[d.lead].mode != 0;
   if (tid < 14) {
     const int pi = (KIND == 1 || tid < 4) ? tid : d.a + tid - 4;
-    double f = W[pi * n + pi];
+    double f = Wsh[pi * n + pi];
     for (int j = 0; j < n; ++j)
-      if ((zb >> j) & 1ull) f += W[pi * n + j];
-    if (f0) f = tid == 0 ? -f : f + W[pi * n];
+      if ((zb >> j) & 1ull) f += Wsh[pi * n + j];
+    if (f0) f = tid == 0 ? -f : f + Wsh[pi * n];
     fl[tid] = f;
   } else if (tid >= 64 && tid <= 64 + n) {
     const int i = tid - 64;
     double t = 0.0;
     if (i == n) {  // old field of bit 0 (kind 1: tile bit 0 is qubit 0)
       if (f0) {
-        t = W[0];
+        t = Wsh[0];
         for (int j = 0; j < n; ++j)
-          if ((zb >> j) & 1ull) t += W[j];
+          if ((zb >> j) & 1ull) t += Wsh[j];
       }
     } else if ((zb >> i) & 1ull) {
-      t = W[i * n + i];
+      t = Wsh[i * n + i];
       for (int j = 0; j < i; ++j)
-        if ((zb >> j) & 1ull) t += W[i * n + j];
+        if ((zb >> j) & 1ull) t += Wsh[i * n + j];
     }
     tmp[i] = t;
-  } else if (tid >= 128 && tid < 128 + A.p) {
-    cf[tid - 128] = A.coef[st * A.p + (tid - 128)];
   }
   if (tid < 196) {
     const int i = tid / 14, j = tid - 14 * i;
     const int pi = (KIND == 1 || i < 4) ? i : d.a + i - 4;
     const int pj = (KIND == 1 || j < 4) ? j : d.a + j - 4;
-    const double w = (i == j) ? 0.0 : W[pi * n + pj];
+    const double w = (i == j) ? 0.0 : Wsh[pi * n + pj];
     Wl[tid] = (f0 && (i == 0) != (j == 0)) ? -w : w;
   }
   lds_barrier();
@@ -594,24 +720,15 @@ fwd14_kernel(F14Args A) {
   PhaseF P;
   double cfix = 0.0, g[6];
   if (PHASE) P = phase_factors<PL>(&T, fl, cblk, lane, wave, cf[d.jb].gp, sr, si);
-  if (PT == P_LAST) thread_energy<PL>(&T, fl, cblk, lane, wave, cfix, g);
-  float2 v[64];
-  if (PT == P_FIRST) {
-    const float amp = (float)exp2(-0.5 * (double)n);
-#pragma unroll
-    for (int r = 0; r < 64; ++r) v[r] = make_float2(amp, 0.0f);
-  } else {
-    load_tile<LA>(v, A.in + st * A.stride + zb, lane, wave, KIND, d.a);
-  }
   bool sw = f0;  // tile bit 0 is flipped
   if (LEAD) {
     const LayerCoef& L = cf[d.lead];
-    half_mixer<LA, PL, MIXLO>(v, buf, lane, wave, mix_t<MIXLO>(L), mix_fx<MIXLO>(L));
+    lead_mixer<KIND, MIXLO>(v, buf, lane, wave, mix_t<MIXLO>(L), L.mode != 0);
   }
   if (PHASE) {
     const LayerCoef& L = cf[d.jb];
     apply_phase(v, KF, P);
-    half_mixer<PL, LA, MIXLO>(v, buf, lane, wave, mix_t<MIXLO>(L), mix_fx<MIXLO>(L));
+    trail_mixer<KIND, MIXLO>(v, buf, lane, wave, mix_t<MIXLO>(L), L.mode != 0);
     if (KIND == 1 && L.mode != 0) sw = !sw;
     store_tile<LA>(v, A.out + st * A.stride + zb, lane, wave, KIND, d.a, sw);
   } else if (PT == P_LEAD) {
@@ -631,6 +748,7 @@ fwd14_kernel(F14Args A) {
       si = 0.0;
     }
     double ae = 0.0, an = 0.0;
+    thread_energy<PL>(&T, fl, cblk, lane, wave, cfix, g);
     reduce_regs(v, &T, cfix, g, ae, an);
     const double s2 = sr * sr + si * si;
     const double se = bsum14(ae, tmp) * s2;
@@ -675,6 +793,7 @@ hipError_t launch_fwd14_pass(const PassDesc& d, int nstates, int S, int p,
   A.part = part;
   A.probs = reinterpret_cast<float*>(probs);
   const uint64_t total = (uint64_t)nstates << (d.n - 14);
+
   if (total > 0xFFFFFFFFull) return hipErrorInvalidValue;
   const dim3 grid((unsigned)total), blk(NT14);
 #define DQ_K(K, M, T) hipLaunchKernelGGL((fwd14_kernel<K, M, T>), grid, blk, 0, stream, A)
