@@ -218,7 +218,9 @@ def main():
     avg_launch_ms = pass_ms / max(launches, 1)
     bytes_per_launch = pass_bytes / max(launches, 1)
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
-    traffic = load_traffic()
+    # counter-derived HBM bytes per launch: taken for the complex64 register-tile pass
+    traffic = (load_traffic() if prec == "c64" and os.environ.get("DQAOA_FWD_KERNEL") != "lds"
+               else None)
     out = {
         "metric": METRIC,
         "value": value,
@@ -252,7 +254,7 @@ def main():
             "peak": PEAK_HBM_GBPS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBPS,
-            "traffic": (traffic if traffic is None else traffic),
+            "traffic": traffic,
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "avg_launch_ms": avg_launch_ms,
             "launches": launches,
