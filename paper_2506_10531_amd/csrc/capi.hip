@@ -223,6 +223,58 @@ bool make_plan_reg14(int n, int p, Plan* P) {
 
 // The register-tile kernel serves complex64 forward evaluations with n >= 15;
 // DQAOA_FWD_KERNEL=lds selects the LDS-tile kernel for every pass instead.
+bool make_plan_reg13(int n, int p, Plan* P) {
+  *P = Plan();
+  if (n < 14 || n > 22 || p < 1 || p > 64) return false;
+  const int a = n - 9 < 4 ? 4 : n - 9;
+  P->K = 13;
+  P->sets = 2;
+  P->c = 4;
+  P->k[0] = P->k[1] = 13;
+  P->a[0] = 13;
+  P->a[1] = a;
+  auto desc = [&](int set, int lead, int ja, int jb) {
+    PassDesc d{};
+    d.n = n;
+    d.set = set;
+    d.lead = lead;
+    d.ja = ja;
+    d.jb = jb;
+    d.k = 13;
+    if (set == 0) {
+      d.c = 13;
+      d.a = 13;
+      d.mixlo = 0;
+      d.kind = 1;
+    } else {
+      d.c = 4;
+      d.a = a;
+      d.mixlo = 4 + (13 - a);
+      d.kind = 2;
+    }
+    return d;
+  };
+  int np = 0;
+  P->pass[np++] = desc(0, -1, 0, 0);
+  for (int j = 0; j < p; ++j) {
+    const int set = (j % 2 == 0) ? 1 : 0;
+    if (j < p - 1) P->pass[np++] = desc(set, j, j + 1, j + 1);
+    else P->pass[np++] = desc(set, j, 1, 0);
+  }
+  for (int i = 0; i < np; ++i)
+    P->pass[i].flags = (i == 0 ? F_INIT : 0) | (i < np - 1 ? F_WRITE : F_REDUCE);
+  P->npass = np;
+  return true;
+}
+
+static bool use_reg13(int op, int prec, int n) {
+  static const bool off = [] {
+    const char* v = getenv("DQAOA_GRAD_KERNEL");
+    return v && strcmp(v, "lds") == 0;
+  }();
+  return !off && op == OP_GRAD && prec == QAOA_C64 && n >= 14 && n <= 22;
+}
+
 static bool use_reg14(int op, int prec, int n) {
   static const bool off = [] {
     const char* v = getenv("DQAOA_FWD_KERNEL");
@@ -233,6 +285,7 @@ static bool use_reg14(int op, int prec, int n) {
 
 bool choose_plan(int op, int prec, int n, int p, Plan* P) {
   if (use_reg14(op, prec, n)) return make_plan_reg14(n, p, P);
+  if (use_reg13(op, prec, n)) return make_plan_reg13(n, p, P);
   return make_plan(n, p, kmax_for(prec, op == OP_GRAD), cpref_for(prec), P);
 }
 
@@ -395,6 +448,28 @@ int enqueue_grad(const Layout& L, char* base, const double* Q,
   const double sb = (double)L.state_bytes * L.nstates;
   auto ck = [&](int i) { return (void*)L.at(base, L.iCk[i]); };
   void* lam = np > 1 ? (void*)L.at(base, L.iLam) : nullptr;
+  if (P.K == 13 && P.pass[0].kind != 0) {
+    // register-tile gradient: checkpoint passes, the seed pass, middle
+    // adjoint passes, and the first pass's adjoint
+    for (int i = 0; i + 1 < np; ++i) {
+      PassDesc d = P.pass[i];
+      TimerScope ts(tm, s, (i == 0 ? 0.0 : sb) + sb);
+      e = launch_fwd13_ckpt_pass(d, ns, S, p, i ? ck(i - 1) : nullptr, ck(i), stride, W, coef, s);
+      if (e != hipSuccess) return hip_error(e, "checkpoint pass");
+    }
+    for (int i = np - 1; i >= 0; --i) {
+      const int shape = i == np - 1 ? 0 : (i == 0 ? 2 : 1);
+      TimerScope ts(tm, s, (shape == 1 ? 3 : 2) * sb);
+      e = launch_bwd13_pass(P.pass[i], shape, ns, S, p, ck(i == np - 1 ? i - 1 : i), lam, stride,
+                            W, coef, part, L.rec_base[i], L.nrec, s);
+      if (e != hipSuccess) return hip_error(e, "adjoint pass");
+    }
+    double* outs[3] = {dgamma, dbeta, expect};
+    int q0[3] = {0, p, 2 * p}, cnt[3] = {p, p, 1};
+    e = launch_reduce_parts(ns, L.nrec, 2 * p + 2, part, outs, q0, cnt, 3, s);
+    if (e != hipSuccess) return hip_error(e, "reduce");
+    return QAOA_OK;
+  }
   // forward sweep, writing a checkpoint per pass
   for (int i = 0; i + 1 < np; ++i) {
     PassDesc d = P.pass[i];

@@ -73,11 +73,26 @@ bool make_plan(int n, int p, int kmax, int cpref, Plan* out);
 // qubits; set 0 = [0, 14), set i >= 1 = [0, 4) + a run of 10 high bits of
 // which it mixes its share of [14, n).
 bool make_plan_reg14(int n, int p, Plan* out);
+// 13-qubit register-tile plan of the complex64 gradient (two sets, 14 <= n
+// <= 22): set 0 = [0, 13), set 1 = [13, n) on tile bits [0, 4) + [a, a + 9).
+// No pending scalars: the checkpoint passes store true-scaled states.
+bool make_plan_reg13(int n, int p, Plan* out);
 
 hipError_t launch_fwd14_pass(const PassDesc& d, int nstates, int S, int p,
                              const void* in, void* out, uint64_t state_stride,
                              const double* W, const LayerCoef* coef,
                              double* part, void* probs, hipStream_t stream);
+// Gradient passes on 13-qubit register tiles (complex64).  The checkpoint
+// pass (first or middle shape) stores its output with every mixer scalar
+// applied; the backward shapes are 0 = seed (the last forward pass fused with
+// its adjoint), 1 = middle, 2 = first.
+hipError_t launch_fwd13_ckpt_pass(const PassDesc& d, int nstates, int S, int p, const void* in,
+                                  void* out, uint64_t stride, const double* W,
+                                  const LayerCoef* coef, hipStream_t stream);
+hipError_t launch_bwd13_pass(const PassDesc& d, int shape, int nstates, int S, int p,
+                             const void* psi, void* lam, uint64_t stride, const double* W,
+                             const LayerCoef* coef, double* part, int rec_base, int nrec,
+                             hipStream_t stream);
 
 // ---- launchers (kernels.hip) ---------------------------------------------
 // prec: 0 = complex128, 1 = complex64.

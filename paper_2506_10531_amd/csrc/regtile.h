@@ -1,0 +1,747 @@
+// Register-tile machinery for complex64 state passes (gfx950), shared by the
+// forward pass on 14-qubit tiles and the adjoint passes on 13-qubit tiles.
+//
+// A tile of 2^K amplitudes (K = R + 8) is held by one work-group of 256
+// threads (4 waves) in registers: R "register" tile bits per thread, 6 lane
+// bits and 2 wave bits.  A layout names which tile bit each register, lane
+// and wave slot holds; register slot 0 is tile bit 0 in every layout (the
+// pivot: LDS transposes move one half of the tile, split on bit 0, at a
+// time).  Butterflies run on register bits only; lane bits 4 and 5 are
+// brought into registers by the gfx950 lane-swap instructions
+// (v_permlane16_swap / v_permlane32_swap exchange a register-pair bit with
+// lane bit 4 / 5), and other bits through an LDS transpose.
+//
+// A geometry G provides:
+//   static constexpr int R;                      register bits
+//   static constexpr int reg_bit(int L, int s);  tile bit of register slot s
+//   static constexpr int lane_bit(int L, int s); tile bit of lane slot s
+//   static constexpr int wave_bit(int L, int s); tile bit of wave slot s
+#pragma once
+
+#include "internal.h"
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace dq {
+namespace rt {
+
+constexpr int NT = 256;
+
+template <class G>
+struct Dim {
+  static constexpr int R = G::R;
+  static constexpr int K = R + 8;              // tile bits
+  static constexpr int NA = 1 << R;            // amplitudes per thread
+  static constexpr int NP = NA / 2;            // register pairs (bit 0)
+  static constexpr int HALF = 1 << (K - 1);    // amplitudes per LDS half
+  static constexpr int PHYS = HALF + (HALF >> 4);
+};
+
+// Padded LDS slot of a half index h (tile index without bit 0): one pad slot
+// per 16.  Additive over disjoint bit sets (a register's slot is the thread's
+// base plus an immediate offset), and half-index bit j moves the slot by 2^j
+// (j < 4) or 2^(j-4) (4 <= j < 8) modulo 16: lane slots 0..3 of every LDS
+// layout take one bit from each class, so a 16-lane group of an access hits
+// 16 distinct 8-byte banks.
+__host__ __device__ constexpr uint32_t phys(uint32_t h) { return h + (h >> 4); }
+
+// Half index of register index q (register slots 1..R-1).
+template <class G, int L>
+__host__ __device__ constexpr uint32_t reg_off(int q) {
+  uint32_t l = 0;
+  for (int s = 1; s < G::R; ++s)
+    if ((q >> (s - 1)) & 1) l |= 1u << G::reg_bit(L, s);
+  return l >> 1;
+}
+
+template <class G, int L>
+__device__ __forceinline__ uint32_t thread_bits(int lane, int wave) {
+  uint32_t l = 0;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) l |= (uint32_t)((lane >> s) & 1) << G::lane_bit(L, s);
+#pragma unroll
+  for (int s = 0; s < 2; ++s) l |= (uint32_t)((wave >> s) & 1) << G::wave_bit(L, s);
+  return l;
+}
+
+// Tile bits of layout L held by lanes and waves; by registers.
+template <class G, int L>
+__host__ __device__ constexpr uint32_t thread_mask() {
+  uint32_t m = 0;
+  for (int s = 0; s < 6; ++s) m |= 1u << G::lane_bit(L, s);
+  for (int s = 0; s < 2; ++s) m |= 1u << G::wave_bit(L, s);
+  return m;
+}
+template <class G, int L>
+__host__ __device__ constexpr uint32_t reg_bits_of() {
+  uint32_t m = 0;
+  for (int s = 0; s < G::R; ++s) m |= 1u << G::reg_bit(L, s);
+  return m;
+}
+
+// Register slots (bit s = slot s) that a round in layout L mixes: its tile
+// bits not mixed earlier in the same half-mixer (DONE) and at or above the
+// pass's first mixed bit.  Compile-time, so a round has no data-dependent
+// control flow.
+template <class G, int L, uint32_t DONE, int MIXLO>
+__host__ __device__ constexpr unsigned reg_mask() {
+  unsigned m = 0;
+  for (int s = 0; s < G::R; ++s) {
+    const int b = G::reg_bit(L, s);
+    if (!((DONE >> b) & 1u) && b >= MIXLO) m |= 1u << s;
+  }
+  return m;
+}
+__host__ __device__ constexpr int popc(unsigned m) {
+  int c = 0;
+  for (; m; m &= m - 1) ++c;
+  return c;
+}
+
+// Global offset of tile index l: set 0 tiles are bits [0, K); the others are
+// bits [0, 4) plus [a, a + K - 4).
+__device__ __forceinline__ uint64_t dep(uint32_t l, int kind, int a) {
+  if (kind == 1) return l;
+  return (uint64_t)(l & 15u) | ((uint64_t)(l >> 4) << a);
+}
+
+// Barrier for LDS hand-offs only: the fence is restricted to the local
+// address space, so it waits for this wave's LDS accesses but not for global
+// loads still in flight.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Move the tile from layout X to layout Y through LDS, one half at a time.
+// With flip, the tile is relabelled on the way: the amplitude at tile index l
+// moves to l ^ M, M = the mixed tile bits [MIXLO, K) without bit 0.  X and Y
+// share only tile bit 0 among their register bits, so every bit of M is a
+// lane or wave bit of X (flipped in the write base) or of Y (flipped in the
+// read base): the relabelling costs nothing per access.
+template <class G, int X, int Y, int MIXLO>
+__device__ __forceinline__ void transpose(float2 (&v)[Dim<G>::NA], float2* buf, int lane,
+                                          int wave, bool flip) {
+  constexpr int K = Dim<G>::K, NP = Dim<G>::NP;
+  constexpr uint32_t M = ((((1u << K) - 1u) >> MIXLO) << MIXLO) & ~1u;
+  constexpr uint32_t M1 = M & thread_mask<G, X>(), M2 = M & ~M1;
+  static_assert((M2 & ~thread_mask<G, Y>()) == 0, "a mixed bit is a register bit of both layouts");
+  static_assert((reg_bits_of<G, X>() & reg_bits_of<G, Y>()) == 1u, "layouts share only the pivot");
+  const uint32_t tx = thread_bits<G, X>(lane, wave) ^ (flip ? M1 : 0u);
+  const uint32_t ty = thread_bits<G, Y>(lane, wave) ^ (flip ? M2 : 0u);
+  float2* const bx = buf + phys(tx >> 1);
+  float2* const by = buf + phys(ty >> 1);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int q = 0; q < NP; ++q) bx[phys(reg_off<G, X>(q))] = v[(q << 1) | h];
+    lds_barrier();
+#pragma unroll
+    for (int q = 0; q < NP; ++q) v[(q << 1) | h] = by[phys(reg_off<G, Y>(q))];
+    lds_barrier();
+  }
+}
+
+// (a0, a1) -> (a0 + i t a1, a1 + i t a0) on every register slot in RM.
+template <class G, unsigned RM>
+__device__ __forceinline__ void mix_round(float2 (&v)[Dim<G>::NA], float t) {
+  constexpr int NP = Dim<G>::NP;
+#pragma unroll
+  for (int s = 0; s < G::R; ++s) {
+    if (!((RM >> s) & 1u)) continue;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      // j-th register index with bit s clear
+      const int r = ((j >> s) << (s + 1)) | (j & ((1 << s) - 1));
+      float2& a0 = v[r];
+      float2& a1 = v[r | (1 << s)];
+      const float x0 = a0.x, y0 = a0.y, x1 = a1.x, y1 = a1.y;
+      a0.x = fmaf(-t, y1, x0);
+      a0.y = fmaf(t, x1, y0);
+      a1.x = fmaf(-t, y0, x1);
+      a1.y = fmaf(t, x0, y1);
+      // bound the butterflies in flight (each needs fresh registers until
+      // both of its inputs are dead)
+      if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+// Exchange register slot SR with lane slot SL (4 or 5) for the whole tile.
+template <class G, int SR, int SL>
+__device__ __forceinline__ void swap_slot(float2 (&v)[Dim<G>::NA]) {
+  static_assert(SL == 4 || SL == 5, "lane slots 4 and 5 only");
+  constexpr int NA = Dim<G>::NA;
+#pragma unroll
+  for (int r = 0; r < NA; ++r) {
+    if ((r >> SR) & 1) continue;
+    float2& a0 = v[r];
+    float2& a1 = v[r | (1 << SR)];
+    const unsigned x0 = __builtin_bit_cast(unsigned, a0.x);
+    const unsigned x1 = __builtin_bit_cast(unsigned, a1.x);
+    const unsigned y0 = __builtin_bit_cast(unsigned, a0.y);
+    const unsigned y1 = __builtin_bit_cast(unsigned, a1.y);
+    unsigned nx0, nx1, ny0, ny1;
+    if (SL == 5) {
+      const auto px = __builtin_amdgcn_permlane32_swap(x0, x1, false, false);
+      const auto py = __builtin_amdgcn_permlane32_swap(y0, y1, false, false);
+      nx0 = px[0], nx1 = px[1], ny0 = py[0], ny1 = py[1];
+    } else {
+      const auto px = __builtin_amdgcn_permlane16_swap(x0, x1, false, false);
+      const auto py = __builtin_amdgcn_permlane16_swap(y0, y1, false, false);
+      nx0 = px[0], nx1 = px[1], ny0 = py[0], ny1 = py[1];
+    }
+    a0 = make_float2(__builtin_bit_cast(float, nx0), __builtin_bit_cast(float, ny0));
+    a1 = make_float2(__builtin_bit_cast(float, nx1), __builtin_bit_cast(float, ny1));
+  }
+}
+
+// Complex helpers.
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+// e^{-i 2 pi rev}.  The angle is reduced in FP64 to t in [-1/2, 1/2], then to
+// an eighth of a turn: q = rint(4 t), theta = 2 pi (t - q / 4) in
+// [-pi/4, pi/4]; sin and cos of theta from their Taylor series through
+// theta^9 and theta^10 (truncation below 2e-9 there), rotated by q quarter
+// turns.
+__device__ __forceinline__ float2 unit(double rev) {
+  const float t = (float)(rev - rint(rev));
+  const float q = rintf(4.0f * t);
+  const float th = 6.28318530717958647692f * fmaf(-0.25f, q, t);
+  const float x = th * th;
+  const float sn =
+      th * fmaf(x, fmaf(x, fmaf(x, fmaf(x, 1.0f / 362880.0f, -1.0f / 5040.0f), 1.0f / 120.0f),
+                        -1.0f / 6.0f),
+                1.0f);
+  const float cs = fmaf(
+      x,
+      fmaf(x, fmaf(x, fmaf(x, fmaf(x, -1.0f / 3628800.0f, 1.0f / 40320.0f), -1.0f / 720.0f),
+                   1.0f / 24.0f),
+           -0.5f),
+      1.0f);
+  // (cos, sin) of theta + q pi / 2
+  const int k = (int)q & 3;
+  const float c = (k & 1) ? ((k & 2) ? sn : -sn) : ((k & 2) ? -cs : cs);
+  const float s = (k & 1) ? ((k & 2) ? -cs : cs) : ((k & 2) ? -sn : sn);
+  return make_float2(c, -s);
+}
+
+// Mixer scalar of one half-mixer on m qubits, multiplied into (re, im): the
+// forward mixer e^{i beta X} is c (I + i tan X) per qubit (mode 0) or
+// i s X (I - i cot X) (mode 1); its inverse e^{-i beta X} is c (I - i tan X)
+// or -i s X (I + i cot X).
+__device__ __forceinline__ void half_scale(const LayerCoef& L, int m, bool inv, double& re,
+                                           double& im) {
+  double r = 1.0, i = 0.0;
+  if (L.mode == 0) {
+    for (int q = 0; q < m; ++q) r *= L.cb;
+  } else {
+    const double sb = inv ? -L.sb : L.sb;
+    for (int q = 0; q < m; ++q) {
+      const double nr = -i * sb, ni = r * sb;
+      r = nr;
+      i = ni;
+    }
+  }
+  const double nr = re * r - im * i, ni = re * i + im * r;
+  re = nr;
+  im = ni;
+}
+// Arithmetic parameter t of a half-mixer, (a0, a1) -> (a0 + i t a1, ...):
+// tan b (mode 0) or -cot b (mode 1) forward, negated for the inverse.
+__device__ __forceinline__ float mix_t(const LayerCoef& L, bool inv) {
+  const float t = L.mode == 0 ? (float)L.tb : -(float)L.tb;
+  return inv ? -t : t;
+}
+
+// Per-tile tables for the phase layout PL (FP64):
+//   Ll[64]    energy of the lane bits alone (with their block fields)
+//   Gl[R][64] field of the lane bits on register slot s
+//   Lw[4]     energy of the wave bits alone
+//   Fw[6][4]  coupling of lane slot i to the wave bits
+//   Gw[R][4]  field of the wave bits on register slot s
+//   Kr[2^R]   couplings among the register bits
+template <int R>
+struct Tables {
+  double Ll[64], Gl[R][64], Lw[4], Fw[6][4], Gw[R][4], Kr[1 << R];
+  static constexpr int N = 64 + R * 64 + 4 + 6 * 4 + R * 4 + (1 << R);
+};
+
+// Entry e of the tables, from the tile-local fields fl[K] and couplings
+// Wl[K][K].
+template <class G, int PL>
+__device__ __forceinline__ void table_entry(Tables<G::R>* T, const double* fl, const double* Wl,
+                                            int e) {
+  constexpr int R = G::R, K = Dim<G>::K;
+  if (e < 64) {
+    double s = 0.0;
+    for (int i = 0; i < 6; ++i)
+      if ((e >> i) & 1) {
+        const int bi = G::lane_bit(PL, i);
+        s += fl[bi];
+        for (int j = 0; j < i; ++j)
+          if ((e >> j) & 1) s += Wl[bi * K + G::lane_bit(PL, j)];
+      }
+    T->Ll[e] = s;
+    return;
+  }
+  e -= 64;
+  if (e < R * 64) {
+    const int sl = e >> 6, x = e & 63, br = G::reg_bit(PL, sl);
+    double s = 0.0;
+    for (int i = 0; i < 6; ++i)
+      if ((x >> i) & 1) s += Wl[br * K + G::lane_bit(PL, i)];
+    T->Gl[sl][x] = s;
+    return;
+  }
+  e -= R * 64;
+  if (e < 4) {
+    double s = 0.0;
+    for (int i = 0; i < 2; ++i)
+      if ((e >> i) & 1) {
+        const int bi = G::wave_bit(PL, i);
+        s += fl[bi];
+        for (int j = 0; j < i; ++j)
+          if ((e >> j) & 1) s += Wl[bi * K + G::wave_bit(PL, j)];
+      }
+    T->Lw[e] = s;
+    return;
+  }
+  e -= 4;
+  if (e < 6 * 4) {
+    const int li = e >> 2, y = e & 3, bl = G::lane_bit(PL, li);
+    double s = 0.0;
+    for (int j = 0; j < 2; ++j)
+      if ((y >> j) & 1) s += Wl[bl * K + G::wave_bit(PL, j)];
+    T->Fw[li][y] = s;
+    return;
+  }
+  e -= 6 * 4;
+  if (e < R * 4) {
+    const int sl = e >> 2, y = e & 3, br = G::reg_bit(PL, sl);
+    double s = 0.0;
+    for (int j = 0; j < 2; ++j)
+      if ((y >> j) & 1) s += Wl[br * K + G::wave_bit(PL, j)];
+    T->Gw[sl][y] = s;
+    return;
+  }
+  e -= R * 4;
+  if (e < (1 << R)) {
+    double s = 0.0;
+    for (int i = 0; i < R; ++i)
+      if ((e >> i) & 1)
+        for (int j = 0; j < i; ++j)
+          if ((e >> j) & 1) s += Wl[G::reg_bit(PL, i) * K + G::reg_bit(PL, j)];
+    T->Kr[e] = s;
+  }
+}
+
+// The thread's cfix and fields g_s in the phase layout (FP64).  Branch-free,
+// so that it does not split the straight-line code around it.
+template <class G, int PL>
+__device__ __forceinline__ void thread_energy(const Tables<G::R>* T, const double* fl,
+                                              double cblk, int lane, int wave, double& cfix,
+                                              double (&g)[G::R]) {
+  double c = cblk + T->Lw[wave] + T->Ll[lane];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const double f = T->Fw[i][wave];
+    c += ((lane >> i) & 1) ? f : 0.0;
+  }
+  cfix = c;
+#pragma unroll
+  for (int s = 0; s < G::R; ++s) g[s] = fl[G::reg_bit(PL, s)] + T->Gl[s][lane] + T->Gw[s][wave];
+}
+
+// Per-thread phase factors of one layer: f0 = e^{-i gamma cfix} times a
+// scalar (sr, si), fs[s] = e^{-i gamma g_s}; gp = gamma / 2 pi (negated to
+// undo the phase).
+template <int R>
+struct PhaseF {
+  float2 f0, fs[R];
+};
+template <class G, int PL>
+__device__ __forceinline__ PhaseF<G::R> phase_factors(const Tables<G::R>* T, const double* fl,
+                                                      double cblk, int lane, int wave, double gp,
+                                                      double sr, double si) {
+  double cfix, g[G::R];
+  thread_energy<G, PL>(T, fl, cblk, lane, wave, cfix, g);
+  PhaseF<G::R> P;
+  P.f0 = cmul(unit(gp * cfix), make_float2((float)sr, (float)si));
+#pragma unroll
+  for (int s = 0; s < G::R; ++s) P.fs[s] = unit(gp * g[s]);
+  return P;
+}
+
+// The factor of every register amplitude r: f0 * prod_{s in r} fs[s] *
+// KF[r], built as a product tree and handed to fn(r, factor).
+template <int R, int S, class F>
+__device__ __forceinline__ void phase_tree(const PhaseF<R>& P, const float2* KF, float2 p, int r,
+                                           F&& fn) {
+  if constexpr (S < 0) {
+    fn(r, cmul(p, KF[r]));
+  } else {
+    phase_tree<R, S - 1>(P, KF, p, r, fn);
+    phase_tree<R, S - 1>(P, KF, cmul(p, P.fs[S]), r | (1 << S), fn);
+    if constexpr (S == 0) __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Phase of one layer on the register amplitudes.
+template <class G>
+__device__ __forceinline__ void apply_phase(float2 (&v)[Dim<G>::NA], const float2* KF,
+                                            const PhaseF<G::R>& P) {
+  phase_tree<G::R, G::R - 1>(P, KF, P.f0, 0,
+                             [&](int r, float2 f) { v[r] = cmul(v[r], f); });
+}
+
+// <C> and norm partial sums of the register amplitudes, FP64, from the
+// thread's cfix and fields g (thread_energy).
+template <class G>
+__device__ __forceinline__ void reduce_regs(const float2 (&v)[Dim<G>::NA], const Tables<G::R>* T,
+                                            double cfix, const double (&g)[G::R], double& ae,
+                                            double& an) {
+  constexpr int R = G::R, LO = 3;
+#pragma unroll
+  for (int hi = 0; hi < (1 << (R - LO)); ++hi) {
+    double ch = cfix;
+#pragma unroll
+    for (int s = LO; s < R; ++s)
+      if ((hi >> (s - LO)) & 1) ch += g[s];
+#pragma unroll
+    for (int lo = 0; lo < (1 << LO); ++lo) {
+      const int r = (hi << LO) | lo;
+      double c = ch + T->Kr[r];
+#pragma unroll
+      for (int s = 0; s < LO; ++s)
+        if ((lo >> s) & 1) c += g[s];
+      const double pz = (double)v[r].x * v[r].x + (double)v[r].y * v[r].y;
+      ae = fma(pz, c, ae);
+      an += pz;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Global load/store of the register tile in layout L (the two amplitudes of a
+// register pair differ in tile bit 0 and move as one 16-byte access).
+template <class G, int L>
+__device__ __forceinline__ void load_tile(float2 (&v)[Dim<G>::NA], const float2* base, int lane,
+                                          int wave, int kind, int a) {
+  const uint64_t tb = dep(thread_bits<G, L>(lane, wave), kind, a);
+#pragma unroll
+  for (int q = 0; q < Dim<G>::NP; ++q) {
+    const uint64_t o = tb + dep(reg_off<G, L>(q) << 1, kind, a);
+    const float4 w = *reinterpret_cast<const float4*>(base + o);
+    v[q << 1] = make_float2(w.x, w.y);
+    v[(q << 1) | 1] = make_float2(w.z, w.w);
+  }
+}
+
+// sw: tile bit 0 is flipped (each register pair is stored in swapped
+// order).  The two orders are separate loops, not per-element selects.
+template <class G, int L, bool SW>
+__device__ __forceinline__ void store_rows(const float2 (&v)[Dim<G>::NA], float2* base,
+                                           uint64_t tb, int kind, int a) {
+#pragma unroll
+  for (int q = 0; q < Dim<G>::NP; ++q) {
+    const uint64_t o = tb + dep(reg_off<G, L>(q) << 1, kind, a);
+    const float2 u = v[(q << 1) | SW], w = v[(q << 1) | !SW];
+    *reinterpret_cast<float4*>(base + o) = make_float4(u.x, u.y, w.x, w.y);
+  }
+}
+template <class G, int L>
+__device__ __forceinline__ void store_tile(const float2 (&v)[Dim<G>::NA], float2* base, int lane,
+                                           int wave, int kind, int a, bool sw) {
+  const uint64_t tb = dep(thread_bits<G, L>(lane, wave), kind, a);
+  if (sw) store_rows<G, L, true>(v, base, tb, kind, a);
+  else store_rows<G, L, false>(v, base, tb, kind, a);
+}
+
+template <class G, int L, bool SW>
+__device__ __forceinline__ void store_prob_rows(const float2 (&v)[Dim<G>::NA], float* base,
+                                                uint64_t tb, int kind, int a, float scale) {
+#pragma unroll
+  for (int q = 0; q < Dim<G>::NP; ++q) {
+    const uint64_t o = tb + dep(reg_off<G, L>(q) << 1, kind, a);
+    const float2 u = v[(q << 1) | SW], w = v[(q << 1) | !SW];
+    *reinterpret_cast<float2*>(base + o) =
+        make_float2(scale * (u.x * u.x + u.y * u.y), scale * (w.x * w.x + w.y * w.y));
+  }
+}
+template <class G, int L>
+__device__ __forceinline__ void store_probs(const float2 (&v)[Dim<G>::NA], float* base, int lane,
+                                            int wave, int kind, int a, float scale, bool sw) {
+  const uint64_t tb = dep(thread_bits<G, L>(lane, wave), kind, a);
+  if (sw) store_prob_rows<G, L, true>(v, base, tb, kind, a, scale);
+  else store_prob_rows<G, L, false>(v, base, tb, kind, a, scale);
+}
+
+// Sum of x over the work-group (red: NT / 64 doubles of LDS).
+__device__ __forceinline__ double block_sum(double x, double* red) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  lds_barrier();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  lds_barrier();
+  double s = 0.0;
+  for (int i = 0; i < NT / 64; ++i) s += red[i];
+  lds_barrier();
+  return s;
+}
+
+// Block bits of tile ti (set kind 1: bits [K, n); kind 2: bits [4, a) and
+// [a + K - 4, n)).
+template <int K>
+__device__ __forceinline__ uint64_t tile_base(uint64_t ti, int kind, int a) {
+  if (kind == 1) return ti << K;
+  const int gap = a - 4;
+  return ((ti & ((1ull << gap) - 1ull)) << 4) | ((ti >> gap) << (a + K - 4));
+}
+
+// LDS context of one tile: the folded Q staged in LDS (Wsh, n x n), the
+// tile-local fields fl[K] (block fields on the tile bits), couplings Wl[K][K]
+// among tile bits and the energy of the block bits (returned).  With f0, the
+// tile-local energy is that of z ^ 1 (tile bit 0 flipped, kind 1 only): the
+// field and couplings of bit 0 change sign, the other fields gain their
+// coupling to bit 0, and the constant gains the old field of bit 0.
+// tmp: n + 1 doubles.  Ends with a barrier.
+template <int K, int KIND>
+__device__ __forceinline__ double tile_context(const double* Wsh, int n, int a, uint64_t zb,
+                                               bool f0, double* fl, double* Wl, double* tmp,
+                                               int tid) {
+  if (tid < K) {
+    const int pi = (KIND == 1 || tid < 4) ? tid : a + tid - 4;
+    double f = Wsh[pi * n + pi];
+    for (int j = 0; j < n; ++j)
+      if ((zb >> j) & 1ull) f += Wsh[pi * n + j];
+    if (f0) f = tid == 0 ? -f : f + Wsh[pi * n];
+    fl[tid] = f;
+  } else if (tid >= 64 && tid <= 64 + n) {
+    const int i = tid - 64;
+    double t = 0.0;
+    if (i == n) {  // old field of bit 0 (kind 1: tile bit 0 is qubit 0)
+      if (f0) {
+        t = Wsh[0];
+        for (int j = 0; j < n; ++j)
+          if ((zb >> j) & 1ull) t += Wsh[j];
+      }
+    } else if ((zb >> i) & 1ull) {
+      t = Wsh[i * n + i];
+      for (int j = 0; j < i; ++j)
+        if ((zb >> j) & 1ull) t += Wsh[i * n + j];
+    }
+    tmp[i] = t;
+  }
+  for (int e = tid; e < K * K; e += NT) {
+    const int i = e / K, j = e - K * i;
+    const int pi = (KIND == 1 || i < 4) ? i : a + i - 4;
+    const int pj = (KIND == 1 || j < 4) ? j : a + j - 4;
+    const double w = (i == j) ? 0.0 : Wsh[pi * n + pj];
+    Wl[e] = (f0 && (i == 0) != (j == 0)) ? -w : w;
+  }
+  lds_barrier();
+  double cblk = 0.0;
+  for (int i = 0; i <= n; ++i) cblk += tmp[i];
+  return cblk;
+}
+
+// Tables of layout PL and the per-tile factors KF[r] = e^{-i 2 pi gp K(r)}
+// (when gp is finite).  Ends with a barrier.
+template <class G, int PL>
+__device__ __forceinline__ void tile_tables(Tables<G::R>* T, float2* KF, const double* fl,
+                                            const double* Wl, bool kf, double gp, int tid) {
+  constexpr int R = G::R, K = Dim<G>::K;
+  for (int e = tid; e < Tables<R>::N; e += NT) table_entry<G, PL>(T, fl, Wl, e);
+  if (kf && tid < (1 << R)) {
+    double k = 0.0;
+    for (int i = 0; i < R; ++i)
+      if ((tid >> i) & 1)
+        for (int j = 0; j < i; ++j)
+          if ((tid >> j) & 1) k += Wl[G::reg_bit(PL, i) * K + G::reg_bit(PL, j)];
+    KF[tid] = unit(gp * k);
+  }
+  lds_barrier();
+}
+
+// Stage the folded Q (n x n) and the state's layer coefficients in LDS while
+// the tile's loads are in flight: the Q reads are issued first, then issue(),
+// the tile loads, then the LDS writes wait for the Q reads only.  Ends with a
+// barrier.
+template <class Issue>
+__device__ __forceinline__ void stage_context(const double* W, int n, const LayerCoef* coef, int p,
+                                              double* Wsh, LayerCoef* cf, int tid, Issue&& issue) {
+  constexpr int NW = (34 * 34 + NT - 1) / NT;
+  const int nn = n * n;
+  double wr[NW];
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const int e = tid + k * NT;
+    wr[k] = e < nn ? W[e] : 0.0;
+  }
+  static_assert(sizeof(LayerCoef) == 40, "layer coefficients move as five doubles");
+  double cv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (tid < p) {
+    const double* c = reinterpret_cast<const double*>(coef + tid);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) cv[k] = c[k];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  issue();
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const int e = tid + k * NT;
+    if (e < nn) Wsh[e] = wr[k];
+  }
+  if (tid < p) {
+    double* c = reinterpret_cast<double*>(cf + tid);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) c[k] = cv[k];
+  }
+  lds_barrier();
+}
+
+// ---- forward pass --------------------------------------------------------------
+
+// Pass shapes (every pass of a register-tile plan is one of these):
+//   P_FIRST  initial state, phase, half-mixer PL -> LA, store (set 0)
+//   P_MID    load, lead half-mixer LA -> PL, phase, half-mixer PL -> LA, store
+//   P_LEAD   load, lead half-mixer LA -> PL, store (sets between the ends of a
+//            layer when there are more than two)
+//   P_LAST   load, lead half-mixer LA -> PL, <C>/norm partials and the
+//            optional probability and state outputs
+enum { P_FIRST = 0, P_MID = 1, P_LEAD = 2, P_LAST = 3 };
+
+struct FwdArgs {
+  PassDesc d;
+  int S, p;
+  const float2* in;
+  float2* out;
+  uint64_t stride;
+  const double* W;
+  const LayerCoef* coef;
+  double* part;
+  float* probs;
+};
+
+// Pass shape of a descriptor, or -1.
+inline int pass_shape(const PassDesc& d, int p) {
+  const bool phase = d.ja <= d.jb;
+  if (phase && (d.ja != d.jb || d.jb < 0 || d.jb >= p)) return -1;
+  if (d.lead >= p) return -1;
+  if (d.flags & F_INIT)
+    return (d.lead < 0 && phase && d.kind == 1 && (d.flags & F_WRITE) && !(d.flags & F_REDUCE))
+               ? P_FIRST
+               : -1;
+  if (d.lead < 0) return -1;
+  if (d.flags & F_REDUCE) return phase ? -1 : P_LAST;
+  if (!(d.flags & F_WRITE)) return -1;
+  return phase ? P_MID : P_LEAD;
+}
+
+// One tile of one pass per work-group (tile index = state * 2^(n-K) + tile
+// of the state).  G::LA is the load/store layout and G::PL<KIND> the phase
+// layout; the pass mixes tile bits [MIXLO, K).  One straight-line body per
+// pass shape keeps the tile's registers in place from load to store.  With
+// TRUE_OUT a stored state carries its pending mixer scalar (the adjoint
+// passes read such states).
+template <class G, int KIND, int MIXLO, int PT, bool TRUE_OUT = false>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+fwd_kernel(FwdArgs A) {
+  using D = Dim<G>;
+  constexpr int K = D::K, NA = D::NA;
+  constexpr int LA = G::LA, PL = G::template PL<KIND>;
+  constexpr bool LEAD = PT != P_FIRST, PHASE = PT == P_FIRST || PT == P_MID;
+  __shared__ float2 buf[D::PHYS];
+  __shared__ Tables<G::R> T;
+  __shared__ double fl[K];
+  __shared__ double Wl[K * K];
+  __shared__ double tmp[40];
+  __shared__ float2 KF[NA];
+  __shared__ LayerCoef cf[64];
+  const PassDesc& d = A.d;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n = d.n, nlog = n - K;
+  const uint64_t tile = blockIdx.x;
+  const uint64_t st = tile >> nlog, ti = tile & ((1ull << nlog) - 1ull);
+  const uint64_t zb = tile_base<K>(ti, KIND, d.a);
+  double* const Wsh = reinterpret_cast<double*>(buf);  // idle until the first transpose
+  float2 v[NA];
+  stage_context(A.W + (size_t)(st / A.S) * n * n, n, A.coef + st * A.p, A.p, Wsh, cf, tid, [&] {
+    if (PT == P_FIRST) {
+      const float amp = (float)exp2(-0.5 * (double)n);
+#pragma unroll
+      for (int r = 0; r < NA; ++r) v[r] = make_float2(amp, 0.0f);
+    } else {
+      load_tile<G, LA>(v, A.in + st * A.stride + zb, lane, wave, KIND, d.a);
+    }
+  });
+  const bool f0 = KIND == 1 && LEAD && cf[d.lead].mode != 0;  // tile bit 0 flipped at PL
+  const double cblk = tile_context<K, KIND>(Wsh, n, d.a, zb, f0, fl, Wl, tmp, tid);
+  if (PT != P_LEAD) tile_tables<G, PL>(&T, KF, fl, Wl, PHASE, PHASE ? cf[d.jb].gp : 0.0, tid);
+
+  // pending mixer scalar (at the phase, or at the outputs of the last pass)
+  double sr = 1.0, si = 0.0;
+  for (int i = 0; i < d.pend_n; ++i) half_scale(cf[d.pend_layer[i]], d.pend_m[i], false, sr, si);
+  if (LEAD) half_scale(cf[d.lead], K - MIXLO, false, sr, si);
+  PhaseF<G::R> P;
+  if (PHASE) P = phase_factors<G, PL>(&T, fl, cblk, lane, wave, cf[d.jb].gp, sr, si);
+  bool sw = f0;  // tile bit 0 is flipped
+  if (LEAD) {
+    const LayerCoef& L = cf[d.lead];
+    G::template lead<KIND, MIXLO>(v, buf, lane, wave, mix_t(L, false), L.mode != 0);
+  }
+  if (PHASE) {
+    const LayerCoef& L = cf[d.jb];
+    apply_phase<G>(v, KF, P);
+    G::template trail<KIND, MIXLO>(v, buf, lane, wave, mix_t(L, false), L.mode != 0);
+    if (KIND == 1 && L.mode != 0) sw = !sw;
+    if (TRUE_OUT) {
+      double tr = 1.0, tq = 0.0;
+      half_scale(L, K - MIXLO, false, tr, tq);
+      const float2 sc = make_float2((float)tr, (float)tq);
+#pragma unroll
+      for (int r = 0; r < NA; ++r) v[r] = cmul(v[r], sc);
+    }
+    store_tile<G, LA>(v, A.out + st * A.stride + zb, lane, wave, KIND, d.a, sw);
+  } else if (PT == P_LEAD) {
+    if (TRUE_OUT) {
+      const float2 sc = make_float2((float)sr, (float)si);
+#pragma unroll
+      for (int r = 0; r < NA; ++r) v[r] = cmul(v[r], sc);
+    }
+    store_tile<G, PL>(v, A.out + st * A.stride + zb, lane, wave, KIND, d.a, sw);
+  } else {
+    // outputs of the final pass carry the pending scalar
+    if (d.flags & F_PROBS) {
+      const float s2 = (float)(sr * sr + si * si);
+      store_probs<G, PL>(v, A.probs + (st << n) + zb, lane, wave, KIND, d.a, s2, sw);
+    }
+    if (d.flags & F_WRITE) {
+      const float2 sc = make_float2((float)sr, (float)si);
+#pragma unroll
+      for (int r = 0; r < NA; ++r) v[r] = cmul(v[r], sc);
+      store_tile<G, PL>(v, A.out + st * A.stride + zb, lane, wave, KIND, d.a, sw);
+      sr = 1.0;
+      si = 0.0;
+    }
+    double ae = 0.0, an = 0.0, cfix, g[G::R];
+    thread_energy<G, PL>(&T, fl, cblk, lane, wave, cfix, g);
+    reduce_regs<G>(v, &T, cfix, g, ae, an);
+    const double s2 = sr * sr + si * si;
+    const double se = block_sum(ae, tmp) * s2;
+    const double sn = block_sum(an, tmp) * s2;
+    if (tid == 0) {
+      double* o = A.part + tile * 2;
+      o[0] = se;
+      o[1] = sn;
+    }
+  }
+}
+
+}  // namespace rt
+}  // namespace dq

@@ -49,12 +49,14 @@ CASES = [(prec, n, p, g) for prec in (0, 1) for g in (0, 1)
 def test_plan_geometry_and_semantics(hctx, prec, n, p, grad):
     kmax = (13 if prec == 0 else 14) - (1 if grad else 0)
     reg14 = prec == 1 and not grad and n >= 15
+    reg13 = prec == 1 and grad and 14 <= n <= 22
     ps = passes(hctx, prec, n, p, grad)
     for i, d in enumerate(ps):
         assert 1 <= d["k"] <= min(kmax, n)
-        assert (d["kind"] != 0) == reg14
-        if reg14:
-            assert d["k"] == 14 and d["kind"] == (1 if d["set"] == 0 else 2)
+        assert (d["kind"] != 0) == (reg14 or reg13)
+        if reg14 or reg13:
+            assert d["k"] == (14 if reg14 else 13)
+            assert d["kind"] == (1 if d["set"] == 0 else 2)
         tb = tile_bits(d, n)
         assert len(tb) == d["k"] and len(set(tb)) == d["k"]
         assert all(0 <= b < n for b in tb)
