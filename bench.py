@@ -29,12 +29,16 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBPS = 8000.0
 METRIC = ("amplitude-layer updates/s + HBM GB/s; sub-QUBO solves/s with p50/p99 "
           "latency")
-KERNEL_SRC = os.path.join(ROOT, "paper_2506_10531_amd", "csrc", "fwd14.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_2506_10531_amd", "csrc", f)
+              for f in ("fwd14.hip", "regtile.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_pass_precision_n24_traffic.json")
 
 
 def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic():
@@ -55,16 +59,19 @@ def parse():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="c64", choices=["c64", "c128"])
-    ap.add_argument("--cpu-sets", type=int, default=8,
+    ap.add_argument("--cpu-sets", type=int, default=16,
                     help="parameter sets the CPU oracle runs (bounded sample)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the complex128 comparison and error report")
-    ap.add_argument("--serving-requests", type=int, default=512,
+    ap.add_argument("--serving-requests", type=int, default=1024,
                     help="requests replayed against the batched solve queue (0: skip)")
-    ap.add_argument("--serving-single", type=int, default=32,
-                    help="requests of the same trace for the one-at-a-time queue")
+    ap.add_argument("--serving-single", type=int, default=-1,
+                    help="requests of the same trace replayed against the one-at-a-time "
+                         "queue (-1: all of them)")
     ap.add_argument("--serving-slots", type=int, default=256)
+    ap.add_argument("--large-steps", type=int, default=3,
+                    help="steps of the n=32 large-state workload (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a 2 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -95,9 +102,9 @@ def serving_leg(requests: int, one_at_a_time: int, max_slots: int, calib: int):
     (n ~ U{12..22} sorted variables, principal submatrix), p = 3, 100 Adam
     evaluations + 1024 shots each, complex64.  A calibration run (all
     `calib` requests at once) gives the saturated rate mu; the Poisson trace
-    arrives at 0.8 mu and is replayed against the batched queue (all
-    `requests`) and, for its first `one_at_a_time` requests, against the
-    one-request-at-a-time queue.  Latency = done - submit (library clock)."""
+    arrives at 0.8 mu and is replayed against the batched queue and against
+    the one-request-at-a-time queue (the first `one_at_a_time` requests, all
+    of them by default).  Latency = done - submit (library clock)."""
     import threading
 
     import numpy as np
@@ -146,6 +153,8 @@ def serving_leg(requests: int, one_at_a_time: int, max_slots: int, calib: int):
     rate = 0.8 * cal["solves_per_s"]
     arr = workloads.poisson_arrivals(requests, rate, W["arrival_seed"])
     batched = run(True, items, arr)
+    if one_at_a_time < 0 or one_at_a_time > requests:
+        one_at_a_time = requests
     single = run(False, items[:one_at_a_time], arr[:one_at_a_time])
     return {
         "workload": (f"{requests} sub-QUBOs of one dense N={W['N']} QUBO, n~U{{"
@@ -156,8 +165,58 @@ def serving_leg(requests: int, one_at_a_time: int, max_slots: int, calib: int):
         "arrival_rate_per_s": rate,
         "batched": batched,
         "one_at_a_time": dict(single, requests=one_at_a_time,
-                              note="first requests of the same trace"),
+                              note=("the same trace" if one_at_a_time == requests
+                                    else "first requests of the same trace")),
         "max_slots": max_slots,
+    }
+
+
+def large_state_leg(steps: int):
+    """The n = 32, p = 2, 4-set complex64 workload (4 x 32 GiB states): one
+    qaoa_expect per step, timed like the main workload, with the register-tile
+    passes' achieved bandwidth from the library's per-launch events."""
+    import torch
+
+    from paper_2506_10531_amd import api, workloads
+
+    W = workloads.WORKLOADS["large_n32"]
+    n, p, S = W["n"], W["p"], W["sets"]
+    dev = torch.device("cuda:0")
+    Q = torch.as_tensor(workloads.qubo(n, W["q_seed"]), device=dev)
+    g, b = workloads.params(S, p, W["p_seed"])
+    gd, bd = torch.as_tensor(g, device=dev), torch.as_tensor(b, device=dev)
+    ctx = api.Context(0)  # its own context: the 128 GiB scratch is freed at close
+    plan = ctx.plan("c64", 1, n, p, S)
+    api.expect(Q, gd, bd, prec="c64", ctx=ctx)  # warm-up (allocates the scratch)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        e = api.expect(Q, gd, bd, prec="c64", ctx=ctx)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.profile(False)
+    launches, pass_ms, pass_bytes = ctx.profile_read(reset=True)
+    en = e.cpu().numpy()[0]
+    del e
+    ctx.close()
+    achieved = (pass_bytes / launches) / (pass_ms / launches * 1e-3) / 1e9
+    floor = S * p * (1 << n) * 16
+    return {
+        "workload": "large_n32: one dense n=32 QUBO, p=2, 4 parameter sets, complex64 "
+                    "(4 x 32 GiB states)",
+        "value": S * p * (1 << n) * steps / wall,
+        "unit": "amplitude-layer updates/s",
+        "ms_per_step": 1e3 * wall / steps,
+        "steps": steps,
+        "hbm_GBps_floor": floor * steps / wall / 1e9,
+        "passes": plan["passes"],
+        "state_reads": plan["state_reads"],
+        "state_writes": plan["state_writes"],
+        "achieved_GBps": achieved,
+        "frac": achieved / PEAK_HBM_GBPS,
+        "expect": [float(x) for x in en],
     }
 
 
@@ -299,17 +358,22 @@ def main():
 
     if not args.no_cpu_baseline:
         import oracle
+        # whole oracle calls on the first k parameter sets, repeated until
+        # about 10 s of host work have been timed
         k = max(1, min(S, args.cpu_sets))
-        t0 = time.perf_counter()
-        eo, _, _ = oracle.expect(Q, g[:k], b[:k])
-        tc = time.perf_counter() - t0
+        calls, tc = 0, 0.0
+        while calls == 0 or (tc < 10.0 and calls < 8):
+            t0 = time.perf_counter()
+            eo, _, _ = oracle.expect(Q, g[:k], b[:k])
+            tc += time.perf_counter() - t0
+            calls += 1
         out["cpu_baseline"] = {
-            "value": k * p * (1 << n) / tc,
+            "value": calls * k * p * (1 << n) / tc,
             "unit": "amplitude-layer updates/s",
             "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"{k} of the {S} parameter sets of the same n=24, p=4 workload "
-                      f"(one oracle call: cost table + {k} x {p} layers), {tc:.1f} s",
+            "sample": f"{calls} oracle call(s) on {k} of the {S} parameter sets of the same "
+                      f"n=24, p=4 workload (cost table + {k} x {p} layers each), {tc:.1f} s",
         }
         if "errors" in out:
             ee = e_main if prec == "c64" else e_other
@@ -321,6 +385,8 @@ def main():
         out["serving"] = serving_leg(args.serving_requests, args.serving_single,
                                      args.serving_slots,
                                      calib=min(256, args.serving_requests))
+    if args.large_steps > 0:
+        out["large_state"] = large_state_leg(args.large_steps)
     print(json.dumps(out))
 
 
