@@ -305,7 +305,8 @@ def main():
                  "state_reads": plan["state_reads"],
                  "state_writes": plan["state_writes"]},
         "roofline": {
-            "kernel": ("fwd_pass_kernel<double>" if prec == "c128" else
+            "kernel": ("fwd_pass_kernel<double>" if prec == "c128" and os.environ.get("DQAOA_FWD_KERNEL") == "lds" else
+                       "fwd13d (complex128 register tile)" if prec == "c128" else
                        "fwd_pass_kernel<float>" if os.environ.get("DQAOA_FWD_KERNEL") == "lds"
                        else "fwd14_kernel (complex64 register tile)"),
             "bound": "hbm",

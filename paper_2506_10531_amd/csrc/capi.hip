@@ -138,32 +138,34 @@ bool make_plan(int n, int p, int kmax, int cpref, Plan* P) {
 }
 
 // Register-tile plan: the same pass sequence as make_plan, with every tile
-// holding 14 qubits.  Set 0 mixes [0, 14); the remaining qubits [14, n) are
-// split into runs of at most 10, and set i's tile is the 4 low bits plus the
-// 10-bit run [a, a + 10) that ends at its mixed run (or at n), so it carries
-// (does not mix) any of those 10 bits below its own run.
-bool make_plan_reg14(int n, int p, Plan* P) {
+// holding K qubits.  Set 0 mixes [0, K); the remaining qubits [K, n) are split
+// into runs of at most K - C, and set i's tile is the C low bits plus the
+// (K - C)-bit run [a, a + K - C) that ends at its mixed run (or at n), so it
+// carries (does not mix) any of those bits below its own run.
+bool make_plan_regtile(int n, int p, int K, int C, Plan* P) {
   *P = Plan();
-  P->K = 14;
-  if (n < 15 || n > 34 || p < 1 || p > 64) return false;
-  const int m = 1 + (n - 14 + 9) / 10;
-  const int rest = n - 14, q = m - 1;
+  P->K = K;
+  const int span = K - C;
+  if (n <= K || n > 34 || p < 1 || p > 64 || span < 1) return false;
+  const int m = 1 + (n - K + span - 1) / span;
+  if (m > 4) return false;
+  const int rest = n - K, q = m - 1;
   int lo[4] = {0}, hi[4] = {0}, a[4] = {0};
   lo[0] = 0;
-  hi[0] = 14;
-  int cur = 14;
+  hi[0] = K;
+  int cur = K;
   for (int i = 1; i < m; ++i) {
     const int run = rest / q + (i - 1 < rest % q ? 1 : 0);
     lo[i] = cur;
     hi[i] = cur + run;
     cur += run;
-    a[i] = hi[i] - 10 < 4 ? 4 : hi[i] - 10;
-    if (a[i] + 10 > n) a[i] = n - 10;
+    a[i] = hi[i] - span < C ? C : hi[i] - span;
+    if (a[i] + span > n) a[i] = n - span;
   }
   P->sets = m;
-  P->c = 4;
+  P->c = C;
   for (int i = 0; i < m; ++i) {
-    P->k[i] = 14;
+    P->k[i] = K;
     P->a[i] = a[i];
   }
   auto desc = [&](int set, int lead, int ja, int jb) {
@@ -173,16 +175,16 @@ bool make_plan_reg14(int n, int p, Plan* P) {
     d.lead = lead;
     d.ja = ja;
     d.jb = jb;
-    d.k = 14;
+    d.k = K;
     if (set == 0) {
-      d.c = 14;
-      d.a = 14;
+      d.c = K;
+      d.a = K;
       d.mixlo = 0;
       d.kind = 1;
     } else {
-      d.c = 4;
+      d.c = C;
       d.a = a[set];
-      d.mixlo = 4 + (lo[set] - a[set]);
+      d.mixlo = C + (lo[set] - a[set]);
       d.kind = 2;
     }
     return d;
@@ -221,8 +223,10 @@ bool make_plan_reg14(int n, int p, Plan* P) {
   return true;
 }
 
-// The register-tile kernel serves complex64 forward evaluations with n >= 15;
-// DQAOA_FWD_KERNEL=lds selects the LDS-tile kernel for every pass instead.
+bool make_plan_reg14(int n, int p, Plan* P) {
+  return n >= 15 && make_plan_regtile(n, p, 14, 4, P);
+}
+
 bool make_plan_reg13(int n, int p, Plan* P) {
   *P = Plan();
   if (n < 14 || n > 22 || p < 1 || p > 64) return false;
@@ -275,16 +279,28 @@ static bool use_reg13(int op, int prec, int n) {
   return !off && op == OP_GRAD && prec == QAOA_C64 && n >= 14 && n <= 22;
 }
 
-static bool use_reg14(int op, int prec, int n) {
+// The register-tile kernels serve forward evaluations with n >= 15
+// (complex64, 14-qubit tiles) or n >= 14 (complex128, 13-qubit tiles);
+// DQAOA_FWD_KERNEL=lds selects the LDS-tile kernel for every pass instead.
+static bool fwd_reg_off() {
   static const bool off = [] {
     const char* v = getenv("DQAOA_FWD_KERNEL");
     return v && strcmp(v, "lds") == 0;
   }();
-  return !off && op != OP_GRAD && prec == QAOA_C64 && n >= 15 && n <= 34;
+  return off;
+}
+
+static bool use_reg14(int op, int prec, int n) {
+  return !fwd_reg_off() && op != OP_GRAD && prec == QAOA_C64 && n >= 15 && n <= 34;
+}
+
+static bool use_reg13d(int op, int prec, int n) {
+  return !fwd_reg_off() && op != OP_GRAD && prec == QAOA_C128 && n >= 14 && n <= 34;
 }
 
 bool choose_plan(int op, int prec, int n, int p, Plan* P) {
   if (use_reg14(op, prec, n)) return make_plan_reg14(n, p, P);
+  if (use_reg13d(op, prec, n)) return make_plan_regtile(n, p, 13, 2, P);
   if (use_reg13(op, prec, n)) return make_plan_reg13(n, p, P);
   return make_plan(n, p, kmax_for(prec, op == OP_GRAD), cpref_for(prec), P);
 }
@@ -383,9 +399,12 @@ int run_forward(const Layout& L, char* base, const double* Q,
     if (d.flags & F_WRITE) bytes += sb;
     if (d.flags & F_PROBS) bytes += sb / 2;
     TimerScope ts(tm, s, bytes);
-    if (d.kind)
+    if (d.kind && L.prec == QAOA_C64)
       e = launch_fwd14_pass(d, (int)L.nstates, L.S, L.p, state,
                             (last && psi) ? psi : state, stride, W, coef, part, probs, s);
+    else if (d.kind)
+      e = launch_fwd13d_pass(d, (int)L.nstates, L.S, L.p, state,
+                             (last && psi) ? psi : state, stride, W, coef, part, probs, s);
     else
       e = launch_fwd_pass(L.prec, d, (int)L.nstates, L.S, L.p, state,
                           (last && psi) ? psi : state, stride, W, coef, part, probs, s);

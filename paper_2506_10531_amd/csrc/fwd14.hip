@@ -45,6 +45,9 @@ using namespace rt;
 // Set 0 mixes in A, A1 | transpose | B, B1 and back in reverse; the other
 // sets in A | transpose | B2 and back.
 struct G14 {
+  using V = float2;
+  using S = float;
+  static constexpr int C = 4;
   static constexpr int R = 6;
   enum { L_A = 0, L_A1 = 1, L_B = 2, L_B1 = 3, L_B2 = 4 };
   static constexpr int LA = L_A;
@@ -74,8 +77,8 @@ struct G14 {
   // Lead half-mixer: from the load layout to the phase layout; trail
   // half-mixer: back.  flip (cot form) relabels the tile in the transpose.
   template <int KIND, int MIXLO>
-  static __device__ __forceinline__ void lead(float2 (&v)[64], float2* buf, int lane, int wave,
-                                              float t, bool flip) {
+  static __device__ __forceinline__ void lead(V (&v)[64], V* buf, int lane, int wave, S t,
+                                              bool flip) {
     if constexpr (KIND == 1) {
       constexpr uint32_t D1 = reg_bits_of<G14, L_A>();
       constexpr uint32_t D2 = D1 | reg_bits_of<G14, L_A1>();
@@ -96,8 +99,8 @@ struct G14 {
     }
   }
   template <int KIND, int MIXLO>
-  static __device__ __forceinline__ void trail(float2 (&v)[64], float2* buf, int lane, int wave,
-                                               float t, bool flip) {
+  static __device__ __forceinline__ void trail(V (&v)[64], V* buf, int lane, int wave, S t,
+                                               bool flip) {
     if constexpr (KIND == 1) {
       constexpr uint32_t D1 = reg_bits_of<G14, L_B1>();
       constexpr uint32_t D2 = D1 | reg_bits_of<G14, L_B>();
@@ -134,13 +137,13 @@ hipError_t launch_fwd14_pass(const PassDesc& d, int nstates, int S, int p,
   A.d = d;
   A.S = S;
   A.p = p;
-  A.in = reinterpret_cast<const float2*>(in);
-  A.out = reinterpret_cast<float2*>(out);
+  A.in = in;
+  A.out = out;
   A.stride = state_stride;
   A.W = W;
   A.coef = coef;
   A.part = part;
-  A.probs = reinterpret_cast<float*>(probs);
+  A.probs = probs;
   const uint64_t total = (uint64_t)nstates << (d.n - 14);
   if (total > 0xFFFFFFFFull) return hipErrorInvalidValue;
   const dim3 grid((unsigned)total), blk(NT);

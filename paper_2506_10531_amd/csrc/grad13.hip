@@ -20,100 +20,14 @@
 // of the layer's mixer, so any point of the undo gives the same value once
 // the factor is divided out), and 2 Im <lambda| C |psi> for d<C>/dgamma_j at
 // the phase layout (the phase leaves it unchanged).
-#include "regtile.h"
+#include "geom13.h"
 
 namespace dq {
 namespace {
 
 using namespace rt;
 
-// Layouts of the 13-qubit tile (register slots 0..4, lane slots 0..5, wave
-// slots 0..1):
-//   L_A   load/store: lane slots are tile bits 1..6
-//   L_A1  L_A with register slots 3, 4 swapped with lane slots 4, 5
-//   L_B   set 0: bits 1..4 in registers
-//   L_B1  L_B with register slots 3, 4 swapped with lane slots 4, 5 (bits
-//         11, 12 in registers); phase layout of set 0
-//   L_B2  other sets: bits 4, 5, 6, 11 in registers
-//   L_B3  L_B2 with register slot 1 swapped with lane slot 4 (bit 12 in
-//         registers); phase layout of the other sets
-// Set 0 mixes in A, A1 | transpose | B, B1 and back in reverse; the other
-// sets in A | transpose | B2, B3 and back.
-struct G13 {
-  static constexpr int R = 5;
-  enum { L_A = 0, L_A1 = 1, L_B = 2, L_B1 = 3, L_B2 = 4, L_B3 = 5 };
-  static constexpr int LA = L_A;
-  template <int KIND>
-  static constexpr int PL = KIND == 1 ? L_B1 : L_B3;
-  static constexpr int reg_bit(int L, int s) {
-    constexpr int t[6][5] = {{0, 7, 8, 9, 10},  {0, 7, 8, 5, 6},  {0, 1, 2, 3, 4},
-                             {0, 1, 2, 11, 12}, {0, 4, 5, 6, 11}, {0, 12, 5, 6, 11}};
-    return t[L][s];
-  }
-  static constexpr int lane_bit(int L, int s) {
-    constexpr int t[6][6] = {{1, 2, 3, 4, 5, 6},  {1, 2, 3, 4, 9, 10}, {5, 6, 7, 8, 11, 12},
-                             {5, 6, 7, 8, 3, 4},  {1, 2, 3, 8, 12, 7}, {1, 2, 3, 8, 4, 7}};
-    return t[L][s];
-  }
-  static constexpr int wave_bit(int L, int s) {
-    constexpr int t[6][2] = {{11, 12}, {11, 12}, {9, 10}, {9, 10}, {9, 10}, {9, 10}};
-    return t[L][s];
-  }
-
-  // Forward half-mixers (used by the checkpoint passes).
-  template <int KIND, int MIXLO>
-  static __device__ __forceinline__ void lead(float2 (&v)[32], float2* buf, int lane, int wave,
-                                              float t, bool flip) {
-    if constexpr (KIND == 1) {
-      constexpr uint32_t D1 = reg_bits_of<G13, L_A>();
-      constexpr uint32_t D2 = D1 | reg_bits_of<G13, L_A1>();
-      constexpr uint32_t D3 = D2 | reg_bits_of<G13, L_B>();
-      mix_round<G13, reg_mask<G13, L_A, 0, MIXLO>()>(v, t);
-      swap_slot<G13, 3, 4>(v);
-      swap_slot<G13, 4, 5>(v);
-      mix_round<G13, reg_mask<G13, L_A1, D1, MIXLO>()>(v, t);
-      transpose<G13, L_A1, L_B, MIXLO>(v, buf, lane, wave, flip);
-      mix_round<G13, reg_mask<G13, L_B, D2, MIXLO>()>(v, t);
-      swap_slot<G13, 3, 4>(v);
-      swap_slot<G13, 4, 5>(v);
-      mix_round<G13, reg_mask<G13, L_B1, D3, MIXLO>()>(v, t);
-    } else {
-      constexpr uint32_t D1 = reg_bits_of<G13, L_A>();
-      constexpr uint32_t D2 = D1 | reg_bits_of<G13, L_B2>();
-      mix_round<G13, reg_mask<G13, L_A, 0, MIXLO>()>(v, t);
-      transpose<G13, L_A, L_B2, MIXLO>(v, buf, lane, wave, flip);
-      mix_round<G13, reg_mask<G13, L_B2, D1, MIXLO>()>(v, t);
-      swap_slot<G13, 1, 4>(v);
-      mix_round<G13, reg_mask<G13, L_B3, D2, MIXLO>()>(v, t);
-    }
-  }
-  template <int KIND, int MIXLO>
-  static __device__ __forceinline__ void trail(float2 (&v)[32], float2* buf, int lane, int wave,
-                                               float t, bool flip) {
-    if constexpr (KIND == 1) {
-      constexpr uint32_t D1 = reg_bits_of<G13, L_B1>();
-      constexpr uint32_t D2 = D1 | reg_bits_of<G13, L_B>();
-      constexpr uint32_t D3 = D2 | reg_bits_of<G13, L_A1>();
-      mix_round<G13, reg_mask<G13, L_B1, 0, MIXLO>()>(v, t);
-      swap_slot<G13, 3, 4>(v);
-      swap_slot<G13, 4, 5>(v);
-      mix_round<G13, reg_mask<G13, L_B, D1, MIXLO>()>(v, t);
-      transpose<G13, L_B, L_A1, MIXLO>(v, buf, lane, wave, flip);
-      mix_round<G13, reg_mask<G13, L_A1, D2, MIXLO>()>(v, t);
-      swap_slot<G13, 3, 4>(v);
-      swap_slot<G13, 4, 5>(v);
-      mix_round<G13, reg_mask<G13, L_A, D3, MIXLO>()>(v, t);
-    } else {
-      constexpr uint32_t D1 = reg_bits_of<G13, L_B3>();
-      constexpr uint32_t D2 = D1 | reg_bits_of<G13, L_B2>();
-      mix_round<G13, reg_mask<G13, L_B3, 0, MIXLO>()>(v, t);
-      swap_slot<G13, 1, 4>(v);
-      mix_round<G13, reg_mask<G13, L_B2, D1, MIXLO>()>(v, t);
-      transpose<G13, L_B2, L_A, MIXLO>(v, buf, lane, wave, flip);
-      mix_round<G13, reg_mask<G13, L_A, D2, MIXLO>()>(v, t);
-    }
-  }
-};
+using G13 = G13T<float2, float, 4>;
 
 using V32 = float2[32];
 
@@ -296,7 +210,7 @@ bwd13_kernel(BwdArgs13 A) {
   const int n = d.n, nlog = n - K;
   const uint64_t tile = blockIdx.x;
   const uint64_t st = tile >> nlog, ti = tile & ((1ull << nlog) - 1ull);
-  const uint64_t zb = tile_base<K>(ti, KIND, d.a);
+  const uint64_t zb = tile_base<K, G::C>(ti, KIND, d.a);
   double* const Wsh = reinterpret_cast<double*>(buf);
   V32 vp, vl;
   stage_context(A.W + (size_t)(st / A.S) * n * n, n, A.coef + st * p, p, Wsh, cf, tid, [&] {
@@ -307,7 +221,7 @@ bwd13_kernel(BwdArgs13 A) {
   // B_SEED) or the trail (B_MID, B_FIRST); its cot form flips tile bit 0
   const LayerCoef& L1 = cf[BT == B_SEED ? d.lead : d.jb];
   const bool f0 = KIND == 1 && L1.mode != 0;
-  const double cblk = tile_context<K, KIND>(Wsh, n, d.a, zb, f0, fl, Wl, tmp, tid);
+  const double cblk = tile_context<K, G::C, KIND>(Wsh, n, d.a, zb, f0, fl, Wl, tmp, tid);
   const double gp_undo = BT == B_SEED ? 0.0 : -cf[d.jb].gp;
   tile_tables<G, PL>(&T, KF, fl, Wl, BT == B_MID, gp_undo, tid);
   const int m = K - MIXLO;
@@ -327,7 +241,7 @@ bwd13_kernel(BwdArgs13 A) {
   const bool sw = KIND == 1 && BT == B_MID && (L1.mode != 0) != (L2.mode != 0);
   // factors that undo the phase of layer jb (B_MID), computed before the
   // undo so that they do not interleave with it
-  PhaseF<G::R> P;
+  PhaseF<G::R, float2> P;
   if (BT == B_MID) P = phase_factors<G, PL>(&T, fl, cblk, lane, wave, gp_undo, 1.0, 0.0);
   double se = 0.0, sn = 0.0, sg = 0.0, sb1 = 0.0, sb2 = 0.0;
   if (BT == B_SEED) {
@@ -415,8 +329,8 @@ hipError_t launch_fwd13_ckpt_pass(const PassDesc& d, int nstates, int S, int p, 
   A.d = d;
   A.S = S;
   A.p = p;
-  A.in = reinterpret_cast<const float2*>(in);
-  A.out = reinterpret_cast<float2*>(out);
+  A.in = in;
+  A.out = out;
   A.stride = stride;
   A.W = W;
   A.coef = coef;

@@ -69,9 +69,11 @@ struct Plan {
 // Builds the pass sequence.  kmax: qubits per LDS tile (13/14 for one
 // complex128/complex64 tile, one less when two tiles share LDS).
 bool make_plan(int n, int p, int kmax, int cpref, Plan* out);
-// Plan for the register-tile kernel (complex64, n >= 15): every tile has 14
-// qubits; set 0 = [0, 14), set i >= 1 = [0, 4) + a run of 10 high bits of
-// which it mixes its share of [14, n).
+// Plan for the register-tile kernels: every tile has K qubits; set 0 =
+// [0, K), set i >= 1 = [0, C) + a run of K - C high bits of which it mixes its
+// share of [K, n).  At most 4 sets, n <= 34.
+bool make_plan_regtile(int n, int p, int K, int C, Plan* out);
+// complex64 register-tile plan (n >= 15): K = 14, C = 4.
 bool make_plan_reg14(int n, int p, Plan* out);
 // 13-qubit register-tile plan of the complex64 gradient (two sets, 14 <= n
 // <= 22): set 0 = [0, 13), set 1 = [13, n) on tile bits [0, 4) + [a, a + 9).
@@ -82,6 +84,11 @@ hipError_t launch_fwd14_pass(const PassDesc& d, int nstates, int S, int p,
                              const void* in, void* out, uint64_t state_stride,
                              const double* W, const LayerCoef* coef,
                              double* part, void* probs, hipStream_t stream);
+// complex128 register-tile pass on 13-qubit tiles (kind-2 sets with C = 2).
+hipError_t launch_fwd13d_pass(const PassDesc& d, int nstates, int S, int p,
+                              const void* in, void* out, uint64_t state_stride,
+                              const double* W, const LayerCoef* coef,
+                              double* part, void* probs, hipStream_t stream);
 // Gradient passes on 13-qubit register tiles (complex64).  The checkpoint
 // pass (first or middle shape) stores its output with every mixer scalar
 // applied; the backward shapes are 0 = seed (the last forward pass fused with

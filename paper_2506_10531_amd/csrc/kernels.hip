@@ -177,6 +177,26 @@ __device__ __forceinline__ void rot(double2& a, double rev) {
   a.y = fma(y, c, -x * s);
 }
 
+// a <- a * e^{-i 2 pi rev} and b <- b * e^{-i 2 pi rev} with one sincos.
+__device__ __forceinline__ void rot2(float2& a, float2& b, double rev) {
+  float s, c;
+  sincospif(2.0f * (float)rev, &s, &c);
+  const float x = a.x, y = a.y, u = b.x, w = b.y;
+  a.x = fmaf(x, c, y * s);
+  a.y = fmaf(y, c, -x * s);
+  b.x = fmaf(u, c, w * s);
+  b.y = fmaf(w, c, -u * s);
+}
+__device__ __forceinline__ void rot2(double2& a, double2& b, double rev) {
+  double s, c;
+  sincospi(2.0 * rev, &s, &c);
+  const double x = a.x, y = a.y, u = b.x, w = b.y;
+  a.x = fma(x, c, y * s);
+  a.y = fma(y, c, -x * s);
+  b.x = fma(u, c, w * s);
+  b.y = fma(w, c, -u * s);
+}
+
 // Phase in revolutions for energy C, reduced in FP64.
 __device__ __forceinline__ double phase_rev(double gp, double C) {
   const double t = gp * C;
@@ -489,9 +509,7 @@ __device__ void bwd_round(typename Cx<T>::V* tp, typename Cx<T>::V* tl, int k,
       for (int v = 0; v < (1 << R); ++v) {
         const double im = (double)b[v].x * a[v].y - (double)b[v].y * a[v].x;
         ag = fma(im, Cv[v], ag);
-        const double rev = phase_rev(-o.gp, Cv[v]);
-        rot(a[v], rev);
-        rot(b[v], rev);
+        rot2(a[v], b[v], phase_rev(-o.gp, Cv[v]));
       }
     }
 #pragma unroll

@@ -12,6 +12,10 @@
 // lane bit 4 / 5), and other bits through an LDS transpose.
 //
 // A geometry G provides:
+//   using V, S;                                  amplitude type (float2 or
+//                                                double2) and its scalar
+//   static constexpr int C;                      contiguous low tile bits of
+//                                                the sets other than set 0
 //   static constexpr int R;                      register bits
 //   static constexpr int reg_bit(int L, int s);  tile bit of register slot s
 //   static constexpr int lane_bit(int L, int s); tile bit of lane slot s
@@ -31,6 +35,8 @@ constexpr int NT = 256;
 
 template <class G>
 struct Dim {
+  using V = typename G::V;
+  using S = typename G::S;
   static constexpr int R = G::R;
   static constexpr int K = R + 8;              // tile bits
   static constexpr int NA = 1 << R;            // amplitudes per thread
@@ -101,10 +107,27 @@ __host__ __device__ constexpr int popc(unsigned m) {
 }
 
 // Global offset of tile index l: set 0 tiles are bits [0, K); the others are
-// bits [0, 4) plus [a, a + K - 4).
+// bits [0, C) plus [a, a + K - C).
+template <int C>
 __device__ __forceinline__ uint64_t dep(uint32_t l, int kind, int a) {
   if (kind == 1) return l;
-  return (uint64_t)(l & 15u) | ((uint64_t)(l >> 4) << a);
+  return (uint64_t)(l & ((1u << C) - 1u)) | ((uint64_t)(l >> C) << a);
+}
+
+// Amplitude and scalar helpers for float2 / double2.
+template <class V>
+__device__ __forceinline__ V mkv(double x, double y) {
+  V r;
+  r.x = (decltype(r.x))x;
+  r.y = (decltype(r.y))y;
+  return r;
+}
+template <class V>
+__device__ __forceinline__ V cmul(V a, V b) {
+  V r;
+  r.x = fma(a.x, b.x, -a.y * b.y);
+  r.y = fma(a.x, b.y, a.y * b.x);
+  return r;
 }
 
 // Barrier for LDS hand-offs only: the fence is restricted to the local
@@ -123,8 +146,8 @@ __device__ __forceinline__ void lds_barrier() {
 // lane or wave bit of X (flipped in the write base) or of Y (flipped in the
 // read base): the relabelling costs nothing per access.
 template <class G, int X, int Y, int MIXLO>
-__device__ __forceinline__ void transpose(float2 (&v)[Dim<G>::NA], float2* buf, int lane,
-                                          int wave, bool flip) {
+__device__ __forceinline__ void transpose(typename G::V (&v)[Dim<G>::NA], typename G::V* buf,
+                                          int lane, int wave, bool flip) {
   constexpr int K = Dim<G>::K, NP = Dim<G>::NP;
   constexpr uint32_t M = ((((1u << K) - 1u) >> MIXLO) << MIXLO) & ~1u;
   constexpr uint32_t M1 = M & thread_mask<G, X>(), M2 = M & ~M1;
@@ -132,8 +155,8 @@ __device__ __forceinline__ void transpose(float2 (&v)[Dim<G>::NA], float2* buf, 
   static_assert((reg_bits_of<G, X>() & reg_bits_of<G, Y>()) == 1u, "layouts share only the pivot");
   const uint32_t tx = thread_bits<G, X>(lane, wave) ^ (flip ? M1 : 0u);
   const uint32_t ty = thread_bits<G, Y>(lane, wave) ^ (flip ? M2 : 0u);
-  float2* const bx = buf + phys(tx >> 1);
-  float2* const by = buf + phys(ty >> 1);
+  typename G::V* const bx = buf + phys(tx >> 1);
+  typename G::V* const by = buf + phys(ty >> 1);
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
 #pragma unroll
@@ -147,7 +170,8 @@ __device__ __forceinline__ void transpose(float2 (&v)[Dim<G>::NA], float2* buf, 
 
 // (a0, a1) -> (a0 + i t a1, a1 + i t a0) on every register slot in RM.
 template <class G, unsigned RM>
-__device__ __forceinline__ void mix_round(float2 (&v)[Dim<G>::NA], float t) {
+__device__ __forceinline__ void mix_round(typename G::V (&v)[Dim<G>::NA], typename G::S t) {
+  using S = typename G::S;
   constexpr int NP = Dim<G>::NP;
 #pragma unroll
   for (int s = 0; s < G::R; ++s) {
@@ -156,13 +180,13 @@ __device__ __forceinline__ void mix_round(float2 (&v)[Dim<G>::NA], float t) {
     for (int j = 0; j < NP; ++j) {
       // j-th register index with bit s clear
       const int r = ((j >> s) << (s + 1)) | (j & ((1 << s) - 1));
-      float2& a0 = v[r];
-      float2& a1 = v[r | (1 << s)];
-      const float x0 = a0.x, y0 = a0.y, x1 = a1.x, y1 = a1.y;
-      a0.x = fmaf(-t, y1, x0);
-      a0.y = fmaf(t, x1, y0);
-      a1.x = fmaf(-t, y0, x1);
-      a1.y = fmaf(t, x0, y1);
+      typename G::V& a0 = v[r];
+      typename G::V& a1 = v[r | (1 << s)];
+      const S x0 = a0.x, y0 = a0.y, x1 = a1.x, y1 = a1.y;
+      a0.x = fma(-t, y1, x0);
+      a0.y = fma(t, x1, y0);
+      a1.x = fma(-t, y0, x1);
+      a1.y = fma(t, x0, y1);
       // bound the butterflies in flight (each needs fresh registers until
       // both of its inputs are dead)
       if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
@@ -170,39 +194,38 @@ __device__ __forceinline__ void mix_round(float2 (&v)[Dim<G>::NA], float t) {
   }
 }
 
-// Exchange register slot SR with lane slot SL (4 or 5) for the whole tile.
+// Exchange register slot SR with lane slot SL (4 or 5) for the whole tile
+// (every 32-bit word of the register pair is swapped).
 template <class G, int SR, int SL>
-__device__ __forceinline__ void swap_slot(float2 (&v)[Dim<G>::NA]) {
+__device__ __forceinline__ void swap_slot(typename G::V (&v)[Dim<G>::NA]) {
   static_assert(SL == 4 || SL == 5, "lane slots 4 and 5 only");
-  constexpr int NA = Dim<G>::NA;
+  using V = typename G::V;
+  constexpr int NA = Dim<G>::NA, NW = sizeof(V) / 4;
+  struct Words {
+    unsigned w[NW];
+  };
 #pragma unroll
   for (int r = 0; r < NA; ++r) {
     if ((r >> SR) & 1) continue;
-    float2& a0 = v[r];
-    float2& a1 = v[r | (1 << SR)];
-    const unsigned x0 = __builtin_bit_cast(unsigned, a0.x);
-    const unsigned x1 = __builtin_bit_cast(unsigned, a1.x);
-    const unsigned y0 = __builtin_bit_cast(unsigned, a0.y);
-    const unsigned y1 = __builtin_bit_cast(unsigned, a1.y);
-    unsigned nx0, nx1, ny0, ny1;
-    if (SL == 5) {
-      const auto px = __builtin_amdgcn_permlane32_swap(x0, x1, false, false);
-      const auto py = __builtin_amdgcn_permlane32_swap(y0, y1, false, false);
-      nx0 = px[0], nx1 = px[1], ny0 = py[0], ny1 = py[1];
-    } else {
-      const auto px = __builtin_amdgcn_permlane16_swap(x0, x1, false, false);
-      const auto py = __builtin_amdgcn_permlane16_swap(y0, y1, false, false);
-      nx0 = px[0], nx1 = px[1], ny0 = py[0], ny1 = py[1];
+    Words w0 = __builtin_bit_cast(Words, v[r]);
+    Words w1 = __builtin_bit_cast(Words, v[r | (1 << SR)]);
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      if (SL == 5) {
+        const auto px = __builtin_amdgcn_permlane32_swap(w0.w[k], w1.w[k], false, false);
+        w0.w[k] = px[0];
+        w1.w[k] = px[1];
+      } else {
+        const auto px = __builtin_amdgcn_permlane16_swap(w0.w[k], w1.w[k], false, false);
+        w0.w[k] = px[0];
+        w1.w[k] = px[1];
+      }
     }
-    a0 = make_float2(__builtin_bit_cast(float, nx0), __builtin_bit_cast(float, ny0));
-    a1 = make_float2(__builtin_bit_cast(float, nx1), __builtin_bit_cast(float, ny1));
+    v[r] = __builtin_bit_cast(V, w0);
+    v[r | (1 << SR)] = __builtin_bit_cast(V, w1);
   }
 }
 
-// Complex helpers.
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
-}
 // e^{-i 2 pi rev}.  The angle is reduced in FP64 to t in [-1/2, 1/2], then to
 // an eighth of a turn: q = rint(4 t), theta = 2 pi (t - q / 4) in
 // [-pi/4, pi/4]; sin and cos of theta from their Taylor series through
@@ -229,6 +252,17 @@ __device__ __forceinline__ float2 unit(double rev) {
   const float s = (k & 1) ? ((k & 2) ? -cs : cs) : ((k & 2) ? -sn : sn);
   return make_float2(c, -s);
 }
+// e^{-i 2 pi rev} in double precision (complex128 states).
+__device__ __forceinline__ double2 unit_d(double rev) {
+  double s, c;
+  sincospi(2.0 * (rev - rint(rev)), &s, &c);
+  return make_double2(c, -s);
+}
+template <class V>
+__device__ __forceinline__ V unitv(double rev) {
+  if constexpr (sizeof(V) == 8) return unit(rev);
+  else return unit_d(rev);
+}
 
 // Mixer scalar of one half-mixer on m qubits, multiplied into (re, im): the
 // forward mixer e^{i beta X} is c (I + i tan X) per qubit (mode 0) or
@@ -253,8 +287,8 @@ __device__ __forceinline__ void half_scale(const LayerCoef& L, int m, bool inv, 
 }
 // Arithmetic parameter t of a half-mixer, (a0, a1) -> (a0 + i t a1, ...):
 // tan b (mode 0) or -cot b (mode 1) forward, negated for the inverse.
-__device__ __forceinline__ float mix_t(const LayerCoef& L, bool inv) {
-  const float t = L.mode == 0 ? (float)L.tb : -(float)L.tb;
+__device__ __forceinline__ double mix_t(const LayerCoef& L, bool inv) {
+  const double t = L.mode == 0 ? L.tb : -L.tb;
   return inv ? -t : t;
 }
 
@@ -360,27 +394,29 @@ __device__ __forceinline__ void thread_energy(const Tables<G::R>* T, const doubl
 // Per-thread phase factors of one layer: f0 = e^{-i gamma cfix} times a
 // scalar (sr, si), fs[s] = e^{-i gamma g_s}; gp = gamma / 2 pi (negated to
 // undo the phase).
-template <int R>
+template <int R, class V>
 struct PhaseF {
-  float2 f0, fs[R];
+  V f0, fs[R];
 };
 template <class G, int PL>
-__device__ __forceinline__ PhaseF<G::R> phase_factors(const Tables<G::R>* T, const double* fl,
-                                                      double cblk, int lane, int wave, double gp,
-                                                      double sr, double si) {
+__device__ __forceinline__ PhaseF<G::R, typename G::V> phase_factors(const Tables<G::R>* T,
+                                                                     const double* fl, double cblk,
+                                                                     int lane, int wave, double gp,
+                                                                     double sr, double si) {
+  using V = typename G::V;
   double cfix, g[G::R];
   thread_energy<G, PL>(T, fl, cblk, lane, wave, cfix, g);
-  PhaseF<G::R> P;
-  P.f0 = cmul(unit(gp * cfix), make_float2((float)sr, (float)si));
+  PhaseF<G::R, V> P;
+  P.f0 = cmul(unitv<V>(gp * cfix), mkv<V>(sr, si));
 #pragma unroll
-  for (int s = 0; s < G::R; ++s) P.fs[s] = unit(gp * g[s]);
+  for (int s = 0; s < G::R; ++s) P.fs[s] = unitv<V>(gp * g[s]);
   return P;
 }
 
 // The factor of every register amplitude r: f0 * prod_{s in r} fs[s] *
 // KF[r], built as a product tree and handed to fn(r, factor).
-template <int R, int S, class F>
-__device__ __forceinline__ void phase_tree(const PhaseF<R>& P, const float2* KF, float2 p, int r,
+template <int R, int S, class V, class F>
+__device__ __forceinline__ void phase_tree(const PhaseF<R, V>& P, const V* KF, V p, int r,
                                            F&& fn) {
   if constexpr (S < 0) {
     fn(r, cmul(p, KF[r]));
@@ -393,16 +429,18 @@ __device__ __forceinline__ void phase_tree(const PhaseF<R>& P, const float2* KF,
 
 // Phase of one layer on the register amplitudes.
 template <class G>
-__device__ __forceinline__ void apply_phase(float2 (&v)[Dim<G>::NA], const float2* KF,
-                                            const PhaseF<G::R>& P) {
+__device__ __forceinline__ void apply_phase(typename G::V (&v)[Dim<G>::NA],
+                                            const typename G::V* KF,
+                                            const PhaseF<G::R, typename G::V>& P) {
   phase_tree<G::R, G::R - 1>(P, KF, P.f0, 0,
-                             [&](int r, float2 f) { v[r] = cmul(v[r], f); });
+                             [&](int r, typename G::V f) { v[r] = cmul(v[r], f); });
 }
 
 // <C> and norm partial sums of the register amplitudes, FP64, from the
 // thread's cfix and fields g (thread_energy).
 template <class G>
-__device__ __forceinline__ void reduce_regs(const float2 (&v)[Dim<G>::NA], const Tables<G::R>* T,
+__device__ __forceinline__ void reduce_regs(const typename G::V (&v)[Dim<G>::NA],
+                                            const Tables<G::R>* T,
                                             double cfix, const double (&g)[G::R], double& ae,
                                             double& an) {
   constexpr int R = G::R, LO = 3;
@@ -427,56 +465,76 @@ __device__ __forceinline__ void reduce_regs(const float2 (&v)[Dim<G>::NA], const
   }
 }
 
-// Global load/store of the register tile in layout L (the two amplitudes of a
-// register pair differ in tile bit 0 and move as one 16-byte access).
+// Global load/store of the register tile in layout L.  The two amplitudes of
+// a register pair differ in tile bit 0 and are adjacent in memory: one
+// 16-byte access for complex64, two for complex128.
 template <class G, int L>
-__device__ __forceinline__ void load_tile(float2 (&v)[Dim<G>::NA], const float2* base, int lane,
-                                          int wave, int kind, int a) {
-  const uint64_t tb = dep(thread_bits<G, L>(lane, wave), kind, a);
+__device__ __forceinline__ void load_tile(typename G::V (&v)[Dim<G>::NA], const typename G::V* base,
+                                          int lane, int wave, int kind, int a) {
+  using V = typename G::V;
+  const uint64_t tb = dep<G::C>(thread_bits<G, L>(lane, wave), kind, a);
 #pragma unroll
   for (int q = 0; q < Dim<G>::NP; ++q) {
-    const uint64_t o = tb + dep(reg_off<G, L>(q) << 1, kind, a);
-    const float4 w = *reinterpret_cast<const float4*>(base + o);
-    v[q << 1] = make_float2(w.x, w.y);
-    v[(q << 1) | 1] = make_float2(w.z, w.w);
+    const uint64_t o = tb + dep<G::C>(reg_off<G, L>(q) << 1, kind, a);
+    if constexpr (sizeof(V) == 8) {
+      const float4 w = *reinterpret_cast<const float4*>(base + o);
+      v[q << 1] = make_float2(w.x, w.y);
+      v[(q << 1) | 1] = make_float2(w.z, w.w);
+    } else {
+      v[q << 1] = base[o];
+      v[(q << 1) | 1] = base[o + 1];
+    }
   }
 }
 
 // sw: tile bit 0 is flipped (each register pair is stored in swapped
 // order).  The two orders are separate loops, not per-element selects.
 template <class G, int L, bool SW>
-__device__ __forceinline__ void store_rows(const float2 (&v)[Dim<G>::NA], float2* base,
-                                           uint64_t tb, int kind, int a) {
+__device__ __forceinline__ void store_rows(const typename G::V (&v)[Dim<G>::NA],
+                                           typename G::V* base, uint64_t tb, int kind, int a) {
+  using V = typename G::V;
 #pragma unroll
   for (int q = 0; q < Dim<G>::NP; ++q) {
-    const uint64_t o = tb + dep(reg_off<G, L>(q) << 1, kind, a);
-    const float2 u = v[(q << 1) | SW], w = v[(q << 1) | !SW];
-    *reinterpret_cast<float4*>(base + o) = make_float4(u.x, u.y, w.x, w.y);
+    const uint64_t o = tb + dep<G::C>(reg_off<G, L>(q) << 1, kind, a);
+    const V u = v[(q << 1) | SW], w = v[(q << 1) | !SW];
+    if constexpr (sizeof(V) == 8) {
+      *reinterpret_cast<float4*>(base + o) = make_float4(u.x, u.y, w.x, w.y);
+    } else {
+      base[o] = u;
+      base[o + 1] = w;
+    }
   }
 }
 template <class G, int L>
-__device__ __forceinline__ void store_tile(const float2 (&v)[Dim<G>::NA], float2* base, int lane,
-                                           int wave, int kind, int a, bool sw) {
-  const uint64_t tb = dep(thread_bits<G, L>(lane, wave), kind, a);
+__device__ __forceinline__ void store_tile(const typename G::V (&v)[Dim<G>::NA],
+                                           typename G::V* base, int lane, int wave, int kind,
+                                           int a, bool sw) {
+  const uint64_t tb = dep<G::C>(thread_bits<G, L>(lane, wave), kind, a);
   if (sw) store_rows<G, L, true>(v, base, tb, kind, a);
   else store_rows<G, L, false>(v, base, tb, kind, a);
 }
 
+// |psi|^2 * scale in the state precision (float for complex64, double for
+// complex128), a register pair per 8- or 16-byte store.
 template <class G, int L, bool SW>
-__device__ __forceinline__ void store_prob_rows(const float2 (&v)[Dim<G>::NA], float* base,
-                                                uint64_t tb, int kind, int a, float scale) {
+__device__ __forceinline__ void store_prob_rows(const typename G::V (&v)[Dim<G>::NA],
+                                                typename G::S* base, uint64_t tb, int kind, int a,
+                                                typename G::S scale) {
+  using V = typename G::V;
+  using S = typename G::S;
 #pragma unroll
   for (int q = 0; q < Dim<G>::NP; ++q) {
-    const uint64_t o = tb + dep(reg_off<G, L>(q) << 1, kind, a);
-    const float2 u = v[(q << 1) | SW], w = v[(q << 1) | !SW];
-    *reinterpret_cast<float2*>(base + o) =
-        make_float2(scale * (u.x * u.x + u.y * u.y), scale * (w.x * w.x + w.y * w.y));
+    const uint64_t o = tb + dep<G::C>(reg_off<G, L>(q) << 1, kind, a);
+    const V u = v[(q << 1) | SW], w = v[(q << 1) | !SW];
+    const S pu = scale * (u.x * u.x + u.y * u.y), pw = scale * (w.x * w.x + w.y * w.y);
+    *reinterpret_cast<V*>(base + o) = mkv<V>(pu, pw);
   }
 }
 template <class G, int L>
-__device__ __forceinline__ void store_probs(const float2 (&v)[Dim<G>::NA], float* base, int lane,
-                                            int wave, int kind, int a, float scale, bool sw) {
-  const uint64_t tb = dep(thread_bits<G, L>(lane, wave), kind, a);
+__device__ __forceinline__ void store_probs(const typename G::V (&v)[Dim<G>::NA],
+                                            typename G::S* base, int lane, int wave, int kind,
+                                            int a, typename G::S scale, bool sw) {
+  const uint64_t tb = dep<G::C>(thread_bits<G, L>(lane, wave), kind, a);
   if (sw) store_prob_rows<G, L, true>(v, base, tb, kind, a, scale);
   else store_prob_rows<G, L, false>(v, base, tb, kind, a, scale);
 }
@@ -493,13 +551,13 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
   return s;
 }
 
-// Block bits of tile ti (set kind 1: bits [K, n); kind 2: bits [4, a) and
-// [a + K - 4, n)).
-template <int K>
+// Block bits of tile ti (set kind 1: bits [K, n); kind 2: bits [C, a) and
+// [a + K - C, n)).
+template <int K, int C>
 __device__ __forceinline__ uint64_t tile_base(uint64_t ti, int kind, int a) {
   if (kind == 1) return ti << K;
-  const int gap = a - 4;
-  return ((ti & ((1ull << gap) - 1ull)) << 4) | ((ti >> gap) << (a + K - 4));
+  const int gap = a - C;
+  return ((ti & ((1ull << gap) - 1ull)) << C) | ((ti >> gap) << (a + K - C));
 }
 
 // LDS context of one tile: the folded Q staged in LDS (Wsh, n x n), the
@@ -509,12 +567,12 @@ __device__ __forceinline__ uint64_t tile_base(uint64_t ti, int kind, int a) {
 // field and couplings of bit 0 change sign, the other fields gain their
 // coupling to bit 0, and the constant gains the old field of bit 0.
 // tmp: n + 1 doubles.  Ends with a barrier.
-template <int K, int KIND>
+template <int K, int C, int KIND>
 __device__ __forceinline__ double tile_context(const double* Wsh, int n, int a, uint64_t zb,
                                                bool f0, double* fl, double* Wl, double* tmp,
                                                int tid) {
   if (tid < K) {
-    const int pi = (KIND == 1 || tid < 4) ? tid : a + tid - 4;
+    const int pi = (KIND == 1 || tid < C) ? tid : a + tid - C;
     double f = Wsh[pi * n + pi];
     for (int j = 0; j < n; ++j)
       if ((zb >> j) & 1ull) f += Wsh[pi * n + j];
@@ -538,8 +596,8 @@ __device__ __forceinline__ double tile_context(const double* Wsh, int n, int a, 
   }
   for (int e = tid; e < K * K; e += NT) {
     const int i = e / K, j = e - K * i;
-    const int pi = (KIND == 1 || i < 4) ? i : a + i - 4;
-    const int pj = (KIND == 1 || j < 4) ? j : a + j - 4;
+    const int pi = (KIND == 1 || i < C) ? i : a + i - C;
+    const int pj = (KIND == 1 || j < C) ? j : a + j - C;
     const double w = (i == j) ? 0.0 : Wsh[pi * n + pj];
     Wl[e] = (f0 && (i == 0) != (j == 0)) ? -w : w;
   }
@@ -552,7 +610,7 @@ __device__ __forceinline__ double tile_context(const double* Wsh, int n, int a, 
 // Tables of layout PL and the per-tile factors KF[r] = e^{-i 2 pi gp K(r)}
 // (when gp is finite).  Ends with a barrier.
 template <class G, int PL>
-__device__ __forceinline__ void tile_tables(Tables<G::R>* T, float2* KF, const double* fl,
+__device__ __forceinline__ void tile_tables(Tables<G::R>* T, typename G::V* KF, const double* fl,
                                             const double* Wl, bool kf, double gp, int tid) {
   constexpr int R = G::R, K = Dim<G>::K;
   for (int e = tid; e < Tables<R>::N; e += NT) table_entry<G, PL>(T, fl, Wl, e);
@@ -562,7 +620,7 @@ __device__ __forceinline__ void tile_tables(Tables<G::R>* T, float2* KF, const d
       if ((tid >> i) & 1)
         for (int j = 0; j < i; ++j)
           if ((tid >> j) & 1) k += Wl[G::reg_bit(PL, i) * K + G::reg_bit(PL, j)];
-    KF[tid] = unit(gp * k);
+    KF[tid] = unitv<typename G::V>(gp * k);
   }
   lds_barrier();
 }
@@ -619,13 +677,13 @@ enum { P_FIRST = 0, P_MID = 1, P_LEAD = 2, P_LAST = 3 };
 struct FwdArgs {
   PassDesc d;
   int S, p;
-  const float2* in;
-  float2* out;
+  const void* in;   // states (float2 or double2 amplitudes)
+  void* out;
   uint64_t stride;
   const double* W;
   const LayerCoef* coef;
   double* part;
-  float* probs;
+  void* probs;      // |psi|^2 in the state precision
 };
 
 // Pass shape of a descriptor, or -1.
@@ -643,6 +701,18 @@ inline int pass_shape(const PassDesc& d, int p) {
   return phase ? P_MID : P_LEAD;
 }
 
+// Tile index of this work-group.  Work-groups are dealt to the 8 XCDs (each
+// with its own L2) in turn.  When a tile's contiguous runs are shorter than a
+// 128 B line, tiles t and t ^ 1 share every line; PAIR maps them to the
+// work-groups 8 apart, i.e. to one XCD back to back, so one L2 sees both
+// halves of each line.  A bijection of [0, gridDim.x) for grids of 16k.
+template <bool PAIR>
+__device__ __forceinline__ uint64_t xcd_tile() {
+  const uint32_t b = blockIdx.x;
+  if (!PAIR || (gridDim.x & 15u)) return b;
+  return (b & ~15u) | ((b & 7u) << 1) | ((b >> 3) & 1u);
+}
+
 // One tile of one pass per work-group (tile index = state * 2^(n-K) + tile
 // of the state).  G::LA is the load/store layout and G::PL<KIND> the phase
 // layout; the pass mixes tile bits [MIXLO, K).  One straight-line body per
@@ -653,79 +723,85 @@ template <class G, int KIND, int MIXLO, int PT, bool TRUE_OUT = false>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
 fwd_kernel(FwdArgs A) {
   using D = Dim<G>;
+  using V = typename G::V;
+  using S = typename G::S;
   constexpr int K = D::K, NA = D::NA;
   constexpr int LA = G::LA, PL = G::template PL<KIND>;
   constexpr bool LEAD = PT != P_FIRST, PHASE = PT == P_FIRST || PT == P_MID;
-  __shared__ float2 buf[D::PHYS];
+  __shared__ V buf[D::PHYS];
   __shared__ Tables<G::R> T;
   __shared__ double fl[K];
   __shared__ double Wl[K * K];
   __shared__ double tmp[40];
-  __shared__ float2 KF[NA];
+  __shared__ V KF[NA];
   __shared__ LayerCoef cf[64];
   const PassDesc& d = A.d;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n = d.n, nlog = n - K;
-  const uint64_t tile = blockIdx.x;
+  const uint64_t tile = xcd_tile<KIND == 2 && (1u << G::C) * sizeof(V) < 128>();
   const uint64_t st = tile >> nlog, ti = tile & ((1ull << nlog) - 1ull);
-  const uint64_t zb = tile_base<K>(ti, KIND, d.a);
+  const uint64_t zb = tile_base<K, G::C>(ti, KIND, d.a);
+  const V* const gin = reinterpret_cast<const V*>(A.in) + st * A.stride + zb;
+  V* const gout = reinterpret_cast<V*>(A.out) + st * A.stride + zb;
   double* const Wsh = reinterpret_cast<double*>(buf);  // idle until the first transpose
-  float2 v[NA];
+  V v[NA];
   stage_context(A.W + (size_t)(st / A.S) * n * n, n, A.coef + st * A.p, A.p, Wsh, cf, tid, [&] {
     if (PT == P_FIRST) {
-      const float amp = (float)exp2(-0.5 * (double)n);
+      const double amp = exp2(-0.5 * (double)n);
 #pragma unroll
-      for (int r = 0; r < NA; ++r) v[r] = make_float2(amp, 0.0f);
+      for (int r = 0; r < NA; ++r) v[r] = mkv<V>(amp, 0.0);
     } else {
-      load_tile<G, LA>(v, A.in + st * A.stride + zb, lane, wave, KIND, d.a);
+      load_tile<G, LA>(v, gin, lane, wave, KIND, d.a);
     }
   });
-  const bool f0 = KIND == 1 && LEAD && cf[d.lead].mode != 0;  // tile bit 0 flipped at PL
-  const double cblk = tile_context<K, KIND>(Wsh, n, d.a, zb, f0, fl, Wl, tmp, tid);
+  // tile bit 0 flipped at PL (only when the pass mixes bit 0)
+  const bool f0 = MIXLO == 0 && LEAD && cf[d.lead].mode != 0;
+  const double cblk = tile_context<K, G::C, KIND>(Wsh, n, d.a, zb, f0, fl, Wl, tmp, tid);
   if (PT != P_LEAD) tile_tables<G, PL>(&T, KF, fl, Wl, PHASE, PHASE ? cf[d.jb].gp : 0.0, tid);
 
   // pending mixer scalar (at the phase, or at the outputs of the last pass)
   double sr = 1.0, si = 0.0;
   for (int i = 0; i < d.pend_n; ++i) half_scale(cf[d.pend_layer[i]], d.pend_m[i], false, sr, si);
   if (LEAD) half_scale(cf[d.lead], K - MIXLO, false, sr, si);
-  PhaseF<G::R> P;
+  PhaseF<G::R, V> P;
   if (PHASE) P = phase_factors<G, PL>(&T, fl, cblk, lane, wave, cf[d.jb].gp, sr, si);
   bool sw = f0;  // tile bit 0 is flipped
   if (LEAD) {
     const LayerCoef& L = cf[d.lead];
-    G::template lead<KIND, MIXLO>(v, buf, lane, wave, mix_t(L, false), L.mode != 0);
+    G::template lead<KIND, MIXLO>(v, buf, lane, wave, (S)mix_t(L, false), L.mode != 0);
   }
   if (PHASE) {
     const LayerCoef& L = cf[d.jb];
     apply_phase<G>(v, KF, P);
-    G::template trail<KIND, MIXLO>(v, buf, lane, wave, mix_t(L, false), L.mode != 0);
-    if (KIND == 1 && L.mode != 0) sw = !sw;
+    G::template trail<KIND, MIXLO>(v, buf, lane, wave, (S)mix_t(L, false), L.mode != 0);
+    if (MIXLO == 0 && L.mode != 0) sw = !sw;
     if (TRUE_OUT) {
       double tr = 1.0, tq = 0.0;
       half_scale(L, K - MIXLO, false, tr, tq);
-      const float2 sc = make_float2((float)tr, (float)tq);
+      const V sc = mkv<V>(tr, tq);
 #pragma unroll
       for (int r = 0; r < NA; ++r) v[r] = cmul(v[r], sc);
     }
-    store_tile<G, LA>(v, A.out + st * A.stride + zb, lane, wave, KIND, d.a, sw);
+    store_tile<G, LA>(v, gout, lane, wave, KIND, d.a, sw);
   } else if (PT == P_LEAD) {
     if (TRUE_OUT) {
-      const float2 sc = make_float2((float)sr, (float)si);
+      const V sc = mkv<V>(sr, si);
 #pragma unroll
       for (int r = 0; r < NA; ++r) v[r] = cmul(v[r], sc);
     }
-    store_tile<G, PL>(v, A.out + st * A.stride + zb, lane, wave, KIND, d.a, sw);
+    store_tile<G, PL>(v, gout, lane, wave, KIND, d.a, sw);
   } else {
     // outputs of the final pass carry the pending scalar
     if (d.flags & F_PROBS) {
-      const float s2 = (float)(sr * sr + si * si);
-      store_probs<G, PL>(v, A.probs + (st << n) + zb, lane, wave, KIND, d.a, s2, sw);
+      const S s2 = (S)(sr * sr + si * si);
+      store_probs<G, PL>(v, reinterpret_cast<S*>(A.probs) + (st << n) + zb, lane, wave, KIND,
+                         d.a, s2, sw);
     }
     if (d.flags & F_WRITE) {
-      const float2 sc = make_float2((float)sr, (float)si);
+      const V sc = mkv<V>(sr, si);
 #pragma unroll
       for (int r = 0; r < NA; ++r) v[r] = cmul(v[r], sc);
-      store_tile<G, PL>(v, A.out + st * A.stride + zb, lane, wave, KIND, d.a, sw);
+      store_tile<G, PL>(v, gout, lane, wave, KIND, d.a, sw);
       sr = 1.0;
       si = 0.0;
     }

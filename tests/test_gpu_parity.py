@@ -75,6 +75,13 @@ def test_multipass_state_and_expect(api, n, p, prec):
     run_case(api, n, p, S=2, prec=prec, B=2 if n < 20 else 1)
 
 
+@pytest.mark.parametrize("n,p", [(23, 2), (25, 3)])
+def test_multiset_c128_state(api, n, p):
+    """complex128 register tiles: two sets up to n = 24, three beyond (with a
+    lead-only pass for the middle set)."""
+    run_case(api, n, p, S=1, prec="c128")
+
+
 def test_plain_n10_all_sets_with_probabilities(api):
     """64 parameter sets, p = 2, complex128, <C> and probabilities."""
     W = workloads.WORKLOADS["plain_n10"]
