@@ -29,26 +29,38 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBPS = 8000.0
 METRIC = ("amplitude-layer updates/s + HBM GB/s; sub-QUBO solves/s with p50/p99 "
           "latency")
-KERNEL_SRC = [os.path.join(ROOT, "paper_2506_10531_amd", "csrc", f)
-              for f in ("fwd14.hip", "regtile.h")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_pass_precision_n24_traffic.json")
+# register-tile forward pass sources per precision, and the committed
+# counter summary of each
+KERNEL_SRC = {
+    "c64": [os.path.join(ROOT, "paper_2506_10531_amd", "csrc", f)
+            for f in ("fwd14.hip", "regtile.h")],
+    "c128": [os.path.join(ROOT, "paper_2506_10531_amd", "csrc", f)
+             for f in ("fwd13d.hip", "geom13.h", "regtile.h")],
+}
+TRAFFIC_FILE = {
+    "c64": os.path.join(ROOT, "profiles", "fwd_pass_precision_n24_traffic.json"),
+    "c128": os.path.join(ROOT, "profiles", "fwd_pass_precision_n24_c128_traffic.json"),
+}
 
 
-def kernel_hash() -> str:
+def kernel_hash(prec: str = "c64") -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SRC:
+    for f in KERNEL_SRC[prec]:
         h.update(open(f, "rb").read())
     return h.hexdigest()[:16]
 
 
-def load_traffic():
+def load_traffic(prec: str = "c64"):
     """HBM bytes per launch of the forward pass from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
+    counter summary, if it was taken on the current kernel source (and the
+    register-tile kernel is the one running)."""
+    if os.environ.get("DQAOA_FWD_KERNEL") == "lds":
+        return None
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = json.load(open(TRAFFIC_FILE[prec]))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_sha") != kernel_hash():
+    if rec.get("kernel_sha") != kernel_hash(prec):
         return None
     return rec.get("bytes_per_launch")
 
@@ -278,8 +290,7 @@ def main():
     bytes_per_launch = pass_bytes / max(launches, 1)
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
     # counter-derived HBM bytes per launch: taken for the complex64 register-tile pass
-    traffic = (load_traffic() if prec == "c64" and os.environ.get("DQAOA_FWD_KERNEL") != "lds"
-               else None)
+    traffic = load_traffic(prec)
     out = {
         "metric": METRIC,
         "value": value,
@@ -341,7 +352,8 @@ def main():
         ach2 = (by2 / max(l2, 1)) / (ms2 / max(l2, 1) * 1e-3) / 1e9
         out[f"{other}_form"] = {"value": updates_per_step * k2 / w2,
                                 "achieved_GBps": ach2, "frac": ach2 / PEAK_HBM_GBPS,
-                                "ms_per_step": 1e3 * w2 / k2}
+                                "ms_per_step": 1e3 * w2 / k2,
+                                "traffic": load_traffic(other)}
         C = oracle.cost_table(Q)
         cmax = float(np.max(np.abs(C)))
         e64 = e_main if prec == "c64" else e_other

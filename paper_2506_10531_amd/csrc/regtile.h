@@ -305,6 +305,10 @@ struct Tables {
   static constexpr int N = 64 + R * 64 + 4 + 6 * 4 + R * 4 + (1 << R);
 };
 
+// 0.0 or 1.0: bit i of x.  Table sums multiply by it instead of branching,
+// so every LDS read of a sum is independent and issued back to back.
+__device__ __forceinline__ double bitd(uint64_t x, int i) { return (double)((x >> i) & 1ull); }
+
 // Entry e of the tables, from the tile-local fields fl[K] and couplings
 // Wl[K][K].
 template <class G, int PL>
@@ -313,13 +317,15 @@ __device__ __forceinline__ void table_entry(Tables<G::R>* T, const double* fl, c
   constexpr int R = G::R, K = Dim<G>::K;
   if (e < 64) {
     double s = 0.0;
-    for (int i = 0; i < 6; ++i)
-      if ((e >> i) & 1) {
-        const int bi = G::lane_bit(PL, i);
-        s += fl[bi];
-        for (int j = 0; j < i; ++j)
-          if ((e >> j) & 1) s += Wl[bi * K + G::lane_bit(PL, j)];
-      }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      const int bi = G::lane_bit(PL, i);
+      double t = fl[bi];
+#pragma unroll
+      for (int j = 0; j < i; ++j) t = fma(bitd(e, j), Wl[bi * K + G::lane_bit(PL, j)], t);
+      s = fma(bitd(e, i), t, s);
+      __builtin_amdgcn_sched_barrier(0);  // at most 6 reads in flight
+    }
     T->Ll[e] = s;
     return;
   }
@@ -327,49 +333,43 @@ __device__ __forceinline__ void table_entry(Tables<G::R>* T, const double* fl, c
   if (e < R * 64) {
     const int sl = e >> 6, x = e & 63, br = G::reg_bit(PL, sl);
     double s = 0.0;
-    for (int i = 0; i < 6; ++i)
-      if ((x >> i) & 1) s += Wl[br * K + G::lane_bit(PL, i)];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) s = fma(bitd(x, i), Wl[br * K + G::lane_bit(PL, i)], s);
     T->Gl[sl][x] = s;
     return;
   }
   e -= R * 64;
   if (e < 4) {
-    double s = 0.0;
-    for (int i = 0; i < 2; ++i)
-      if ((e >> i) & 1) {
-        const int bi = G::wave_bit(PL, i);
-        s += fl[bi];
-        for (int j = 0; j < i; ++j)
-          if ((e >> j) & 1) s += Wl[bi * K + G::wave_bit(PL, j)];
-      }
-    T->Lw[e] = s;
+    const int b0 = G::wave_bit(PL, 0), b1 = G::wave_bit(PL, 1);
+    const double t1 = fl[b1] + bitd(e, 0) * Wl[b1 * K + b0];
+    T->Lw[e] = fma(bitd(e, 0), fl[b0], bitd(e, 1) * t1);
     return;
   }
   e -= 4;
   if (e < 6 * 4) {
     const int li = e >> 2, y = e & 3, bl = G::lane_bit(PL, li);
-    double s = 0.0;
-    for (int j = 0; j < 2; ++j)
-      if ((y >> j) & 1) s += Wl[bl * K + G::wave_bit(PL, j)];
-    T->Fw[li][y] = s;
+    T->Fw[li][y] = fma(bitd(y, 0), Wl[bl * K + G::wave_bit(PL, 0)],
+                       bitd(y, 1) * Wl[bl * K + G::wave_bit(PL, 1)]);
     return;
   }
   e -= 6 * 4;
   if (e < R * 4) {
     const int sl = e >> 2, y = e & 3, br = G::reg_bit(PL, sl);
-    double s = 0.0;
-    for (int j = 0; j < 2; ++j)
-      if ((y >> j) & 1) s += Wl[br * K + G::wave_bit(PL, j)];
-    T->Gw[sl][y] = s;
+    T->Gw[sl][y] = fma(bitd(y, 0), Wl[br * K + G::wave_bit(PL, 0)],
+                       bitd(y, 1) * Wl[br * K + G::wave_bit(PL, 1)]);
     return;
   }
   e -= R * 4;
   if (e < (1 << R)) {
     double s = 0.0;
-    for (int i = 0; i < R; ++i)
-      if ((e >> i) & 1)
-        for (int j = 0; j < i; ++j)
-          if ((e >> j) & 1) s += Wl[G::reg_bit(PL, i) * K + G::reg_bit(PL, j)];
+#pragma unroll
+    for (int i = 1; i < R; ++i) {
+      double t = 0.0;
+#pragma unroll
+      for (int j = 0; j < i; ++j) t = fma(bitd(e, j), Wl[G::reg_bit(PL, i) * K + G::reg_bit(PL, j)], t);
+      s = fma(bitd(e, i), t, s);
+      __builtin_amdgcn_sched_barrier(0);
+    }
     T->Kr[e] = s;
   }
 }
@@ -434,6 +434,15 @@ __device__ __forceinline__ void apply_phase(typename G::V (&v)[Dim<G>::NA],
                                             const PhaseF<G::R, typename G::V>& P) {
   phase_tree<G::R, G::R - 1>(P, KF, P.f0, 0,
                              [&](int r, typename G::V f) { v[r] = cmul(v[r], f); });
+}
+
+// The register amplitudes set to their phase factors (the state before the
+// first phase is uniform and its amplitude is folded into P.f0).
+template <class G>
+__device__ __forceinline__ void init_phase(typename G::V (&v)[Dim<G>::NA],
+                                           const typename G::V* KF,
+                                           const PhaseF<G::R, typename G::V>& P) {
+  phase_tree<G::R, G::R - 1>(P, KF, P.f0, 0, [&](int r, typename G::V f) { v[r] = f; });
 }
 
 // <C> and norm partial sums of the register amplitudes, FP64, from the
@@ -574,25 +583,20 @@ __device__ __forceinline__ double tile_context(const double* Wsh, int n, int a, 
   if (tid < K) {
     const int pi = (KIND == 1 || tid < C) ? tid : a + tid - C;
     double f = Wsh[pi * n + pi];
-    for (int j = 0; j < n; ++j)
-      if ((zb >> j) & 1ull) f += Wsh[pi * n + j];
+#pragma unroll 8
+    for (int j = 0; j < n; ++j) f = fma(bitd(zb, j), Wsh[pi * n + j], f);
     if (f0) f = tid == 0 ? -f : f + Wsh[pi * n];
     fl[tid] = f;
   } else if (tid >= 64 && tid <= 64 + n) {
+    // block energy: row i of the block bits (i < n), or the old field of
+    // tile bit 0 when it is flipped (i = n; kind 1: tile bit 0 is qubit 0)
     const int i = tid - 64;
-    double t = 0.0;
-    if (i == n) {  // old field of bit 0 (kind 1: tile bit 0 is qubit 0)
-      if (f0) {
-        t = Wsh[0];
-        for (int j = 0; j < n; ++j)
-          if ((zb >> j) & 1ull) t += Wsh[j];
-      }
-    } else if ((zb >> i) & 1ull) {
-      t = Wsh[i * n + i];
-      for (int j = 0; j < i; ++j)
-        if ((zb >> j) & 1ull) t += Wsh[i * n + j];
-    }
-    tmp[i] = t;
+    const bool fr = i == n;
+    const int row = fr ? 0 : i, cnt = fr ? n : i;
+    double t = Wsh[row * n + row];
+#pragma unroll 8
+    for (int j = 0; j < cnt; ++j) t = fma(bitd(zb, j), Wsh[row * n + j], t);
+    tmp[i] = fr ? (f0 ? t : 0.0) : bitd(zb, i) * t;
   }
   for (int e = tid; e < K * K; e += NT) {
     const int i = e / K, j = e - K * i;
@@ -613,13 +617,19 @@ template <class G, int PL>
 __device__ __forceinline__ void tile_tables(Tables<G::R>* T, typename G::V* KF, const double* fl,
                                             const double* Wl, bool kf, double gp, int tid) {
   constexpr int R = G::R, K = Dim<G>::K;
+#pragma unroll 1
   for (int e = tid; e < Tables<R>::N; e += NT) table_entry<G, PL>(T, fl, Wl, e);
   if (kf && tid < (1 << R)) {
     double k = 0.0;
-    for (int i = 0; i < R; ++i)
-      if ((tid >> i) & 1)
-        for (int j = 0; j < i; ++j)
-          if ((tid >> j) & 1) k += Wl[G::reg_bit(PL, i) * K + G::reg_bit(PL, j)];
+#pragma unroll
+    for (int i = 1; i < R; ++i) {
+      double t = 0.0;
+#pragma unroll
+      for (int j = 0; j < i; ++j)
+        t = fma(bitd(tid, j), Wl[G::reg_bit(PL, i) * K + G::reg_bit(PL, j)], t);
+      k = fma(bitd(tid, i), t, k);
+      __builtin_amdgcn_sched_barrier(0);
+    }
     KF[tid] = unitv<typename G::V>(gp * k);
   }
   lds_barrier();
@@ -746,13 +756,7 @@ fwd_kernel(FwdArgs A) {
   double* const Wsh = reinterpret_cast<double*>(buf);  // idle until the first transpose
   V v[NA];
   stage_context(A.W + (size_t)(st / A.S) * n * n, n, A.coef + st * A.p, A.p, Wsh, cf, tid, [&] {
-    if (PT == P_FIRST) {
-      const double amp = exp2(-0.5 * (double)n);
-#pragma unroll
-      for (int r = 0; r < NA; ++r) v[r] = mkv<V>(amp, 0.0);
-    } else {
-      load_tile<G, LA>(v, gin, lane, wave, KIND, d.a);
-    }
+    if (PT != P_FIRST) load_tile<G, LA>(v, gin, lane, wave, KIND, d.a);
   });
   // tile bit 0 flipped at PL (only when the pass mixes bit 0)
   const bool f0 = MIXLO == 0 && LEAD && cf[d.lead].mode != 0;
@@ -764,6 +768,9 @@ fwd_kernel(FwdArgs A) {
   for (int i = 0; i < d.pend_n; ++i) half_scale(cf[d.pend_layer[i]], d.pend_m[i], false, sr, si);
   if (LEAD) half_scale(cf[d.lead], K - MIXLO, false, sr, si);
   PhaseF<G::R, V> P;
+  // the first pass starts from the uniform amplitude 2^{-n/2}: it folds into
+  // the thread factor, and the phase factors become the amplitudes
+  if (PT == P_FIRST) sr *= exp2(-0.5 * (double)n), si *= exp2(-0.5 * (double)n);
   if (PHASE) P = phase_factors<G, PL>(&T, fl, cblk, lane, wave, cf[d.jb].gp, sr, si);
   bool sw = f0;  // tile bit 0 is flipped
   if (LEAD) {
@@ -772,7 +779,8 @@ fwd_kernel(FwdArgs A) {
   }
   if (PHASE) {
     const LayerCoef& L = cf[d.jb];
-    apply_phase<G>(v, KF, P);
+    if (PT == P_FIRST) init_phase<G>(v, KF, P);
+    else apply_phase<G>(v, KF, P);
     G::template trail<KIND, MIXLO>(v, buf, lane, wave, (S)mix_t(L, false), L.mode != 0);
     if (MIXLO == 0 && L.mode != 0) sw = !sw;
     if (TRUE_OUT) {
