@@ -250,6 +250,79 @@ int qaoa_wait(qaoa_queue* q, uint64_t ticket, int64_t timeout_ns,
 int qaoa_cancel(qaoa_queue* q, uint64_t ticket);
 int qaoa_queue_get_stats(qaoa_queue* q, qaoa_queue_stats* out);
 
+/* ---- DQAOA outer cycle (Sec. V) ------------------------------------------
+ * The classical steps around the sub-QUBO solves, on the device, for one
+ * dense N x N QUBO Q (device, row-major FP64) and a global 0/1 solution x
+ * (device, one byte per variable, non-zero = 1; E(x) = x^T Q x, Eq. (1)).
+ * 1 <= N <= 65536; windows hold 1 <= k <= min(N, 64) variables.  Device
+ * buffers are caller-owned; calls are stream-ordered and use no context
+ * scratch.  Fixed-order FP64 sums make every result reproducible. */
+
+/* Impact factors (Sec. V-A-2): impact[i] = E(x with x_i flipped) - E(x),
+ * from one pass over Q via g = (Q + Q^T) x: impact[i] = d_i (Q_ii + g_i -
+ * 2 Q_ii x_i), d_i = 1 - 2 x_i.  field [N] receives g (required: it also
+ * holds Q x in between); energy [1] receives E(x) (nullable); order [N]
+ * receives the variables ranked by |impact| (largest first, ties to the
+ * smaller index, NaN last), always a permutation of [0, N) (nullable). */
+int qaoa_impact(qaoa_ctx* ctx, int N, const double* Q, const uint8_t* x,
+                double* impact, double* field, int32_t* order, double* energy,
+                qaoa_stream_t stream);
+
+/* IFD windows (the decomposition algorithm of Sec. V-A-2): window t of m is
+ * order[(t*stride + r) mod N], r < k, sorted ascending, into choices
+ * [m][k] int32.  stride 1 is the algorithm as printed (overlapping
+ * windows); stride k gives disjoint windows.  order must be a permutation
+ * of [0, N) (as qaoa_impact writes it). */
+int qaoa_ifd_choices(qaoa_ctx* ctx, int N, const int32_t* order, int m, int k,
+                     int stride, int32_t* choices, qaoa_stream_t stream);
+
+/* Sub-QUBOs (Sec. V, first step): subq[t] = Q[S_t, S_t], [m][k][k] FP64,
+ * with S_t = choices[t][0..k) (ascending and distinct; bit r of a sub-QUBO
+ * basis index is variable choices[t][r]).  Random decomposition (Sec.
+ * V-A-1) passes randomly drawn windows here.  An index outside [0, N) sets
+ * its row and column to NaN. */
+int qaoa_decompose(qaoa_ctx* ctx, int N, const double* Q, int m, int k,
+                   const int32_t* choices, double* subq, qaoa_stream_t stream);
+
+/* Aggregation (Sec. V, third step): for t = 0..m-1 in order, the variables
+ * of window t take the bits of subsol[t] (bit r -> choices[t][r]); the
+ * change is kept only if it lowers E strictly.  field and energy must hold
+ * (Q + Q^T) x and E(x) on entry (qaoa_impact) and are kept current, x is
+ * updated in place; accepted [m] int32 (nullable) gets 1 / 0, or -1 for a
+ * window holding an index outside [0, N) (skipped). */
+int qaoa_aggregate(qaoa_ctx* ctx, int N, const double* Q, uint8_t* x,
+                   double* field, double* energy, int m, int k,
+                   const int32_t* choices, const uint64_t* subsol,
+                   int32_t* accepted, qaoa_stream_t stream);
+
+/* Bytes of device workspace qaoa_dqaoa_cycle needs (0 for invalid sizes). */
+size_t qaoa_cycle_workspace(int N, int m, int k);
+
+enum { QAOA_DECOMP_GIVEN = 0, QAOA_DECOMP_IFD = 1 };
+
+typedef struct {
+  double decompose_ms;  /* impact factors, windows, sub-QUBO gather + copy */
+  double solve_ms;      /* the m sub-QUBO solves on the queue */
+  double aggregate_ms;  /* aggregation of the best samples */
+  int accepted;         /* windows whose sub-solution was kept */
+  double energy;        /* E(x) after the cycle */
+} qaoa_cycle_stats;
+
+/* One DQAOA cycle (Sec. V): windows from the impact factors of x (mode
+ * QAOA_DECOMP_IFD, with stride) or from choices (device [m][k], mode
+ * QAOA_DECOMP_GIVEN, e.g. random windows); the m sub-QUBOs solved on queue
+ * q (k <= 22 qubits each; initial parameters gamma0/beta0 are host arrays
+ * of the queue's p; request t samples with seed + t); their best samples
+ * aggregated into x.  field and energy [1] (device) receive (Q + Q^T) x and
+ * E(x), work is a device buffer of qaoa_cycle_workspace(N, m, k) bytes.
+ * Blocks until done (host stats, nullable).  A failed solve cancels the
+ * remaining requests and returns its error; x is then unchanged. */
+int qaoa_dqaoa_cycle(qaoa_ctx* ctx, qaoa_queue* q, int N, const double* Q,
+                     uint8_t* x, double* field, double* energy, int mode, int m,
+                     int k, int stride, const int32_t* choices,
+                     const double* gamma0, const double* beta0, uint64_t seed,
+                     void* work, qaoa_cycle_stats* stats, qaoa_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -41,7 +41,12 @@ EXPORTS = [
     "qaoa_profile_enable", "qaoa_profile_read", "qaoa_queue_create",
     "qaoa_queue_destroy", "qaoa_submit", "qaoa_poll", "qaoa_wait",
     "qaoa_cancel", "qaoa_queue_get_stats",
+    "qaoa_impact", "qaoa_ifd_choices", "qaoa_decompose", "qaoa_aggregate",
+    "qaoa_cycle_workspace", "qaoa_dqaoa_cycle",
 ]
+
+QAOA_DECOMP_GIVEN = 0
+QAOA_DECOMP_IFD = 1
 
 
 class QaoaError(RuntimeError):
@@ -80,6 +85,12 @@ class SolveResult(ctypes.Structure):
                 ("expect", ctypes.c_double), ("best_z", ctypes.c_uint64),
                 ("best_c", ctypes.c_double), ("t_submit_ns", ctypes.c_int64),
                 ("t_admit_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64)]
+
+
+class CycleStats(ctypes.Structure):
+    _fields_ = [("decompose_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("aggregate_ms", ctypes.c_double), ("accepted", ctypes.c_int),
+                ("energy", ctypes.c_double)]
 
 
 class QueueStats(ctypes.Structure):
@@ -128,9 +139,17 @@ def load():
     L.qaoa_wait.argtypes = [vp, u64, ctypes.c_int64, ctypes.POINTER(SolveResult), vp]
     L.qaoa_cancel.argtypes = [vp, u64]
     L.qaoa_queue_get_stats.argtypes = [vp, ctypes.POINTER(QueueStats)]
+    L.qaoa_impact.argtypes = [vp, i, dp, dp, dp, dp, dp, dp, vp]
+    L.qaoa_ifd_choices.argtypes = [vp, i, dp, i, i, i, dp, vp]
+    L.qaoa_decompose.argtypes = [vp, i, dp, i, i, dp, dp, vp]
+    L.qaoa_aggregate.argtypes = [vp, i, dp, dp, dp, dp, i, i, dp, dp, dp, vp]
+    L.qaoa_cycle_workspace.argtypes = [i, i, i]
+    L.qaoa_dqaoa_cycle.argtypes = [vp, vp, i, dp, dp, dp, dp, i, i, i, i, dp, dp, dp,
+                                   u64, dp, ctypes.POINTER(CycleStats), vp]
     for name in EXPORTS:
         if name not in ("qaoa_last_error", "qaoa_version"):
             getattr(L, name).restype = ctypes.c_int
+    L.qaoa_cycle_workspace.restype = sz
     _lib = L
     return L
 

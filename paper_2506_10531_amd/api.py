@@ -226,3 +226,69 @@ class QAOAExpect(torch.autograd.Function):
         dg, db = ctx.saved_tensors
         go = go.reshape(dg.shape[:-1]).unsqueeze(-1)
         return None, (dg * go).view(ctx.gshape), (db * go).view(ctx.gshape), None
+
+
+# ---- DQAOA outer cycle (Sec. V) -------------------------------------------
+
+def impact(Q, x, ctx=None):
+    """Impact factors of the global solution x (uint8 [N]) on Q [N, N]:
+    (impact [N], field (Q + Q^T) x [N], order [N] int32, energy [1])."""
+    Q = _dev(Q, "Q")
+    x = _dev(x, "x", torch.uint8)
+    N = Q.shape[0]
+    if Q.shape != (N, N) or x.shape != (N,):
+        raise ValueError("Q must be [N, N] and x [N]")
+    ctx = ctx or default_context(Q.device.index)
+    dev = Q.device
+    imp = torch.empty(N, dtype=torch.float64, device=dev)
+    field = torch.empty(N, dtype=torch.float64, device=dev)
+    order = torch.empty(N, dtype=torch.int32, device=dev)
+    e = torch.empty(1, dtype=torch.float64, device=dev)
+    _lib.check(_lib.load().qaoa_impact(ctx.h, N, _ptr(Q), _ptr(x), _ptr(imp), _ptr(field),
+                                       _ptr(order), _ptr(e), _stream()))
+    return imp, field, order, e
+
+
+def ifd_choices(order, m: int, k: int, stride: int = 1, ctx=None):
+    """IFD windows [m, k] int32 from a ranking (qaoa_ifd_choices)."""
+    order = _dev(order, "order", torch.int32)
+    N = order.shape[0]
+    ctx = ctx or default_context(order.device.index)
+    ch = torch.empty((m, k), dtype=torch.int32, device=order.device)
+    _lib.check(_lib.load().qaoa_ifd_choices(ctx.h, N, _ptr(order), m, k, stride, _ptr(ch),
+                                            _stream()))
+    return ch
+
+
+def decompose(Q, choices, ctx=None):
+    """Sub-QUBOs Q[S_t, S_t] [m, k, k] of the windows choices [m, k] int32."""
+    Q = _dev(Q, "Q")
+    choices = _dev(choices, "choices", torch.int32)
+    N = Q.shape[0]
+    m, k = choices.shape
+    ctx = ctx or default_context(Q.device.index)
+    sq = torch.empty((m, k, k), dtype=torch.float64, device=Q.device)
+    _lib.check(_lib.load().qaoa_decompose(ctx.h, N, _ptr(Q), m, k, _ptr(choices), _ptr(sq),
+                                          _stream()))
+    return sq
+
+
+def aggregate(Q, x, field, energy, choices, subsol, ctx=None):
+    """Fold sub-solutions subsol [m] uint64 into x, field and energy in
+    place (qaoa_aggregate); returns accepted [m] int32."""
+    Q = _dev(Q, "Q")
+    for t, nm, dt in ((x, "x", torch.uint8), (field, "field", torch.float64),
+                      (energy, "energy", torch.float64)):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dt and t.is_contiguous()):
+            raise TypeError(f"{nm} must be a contiguous {dt} GPU tensor (updated in place)")
+    choices = _dev(choices, "choices", torch.int32)
+    subsol = _dev(subsol, "subsol",
+                  subsol.dtype if subsol.dtype in (torch.int64, torch.uint64) else torch.uint64)
+    N = Q.shape[0]
+    m, k = choices.shape
+    ctx = ctx or default_context(Q.device.index)
+    acc = torch.empty(m, dtype=torch.int32, device=Q.device)
+    _lib.check(_lib.load().qaoa_aggregate(ctx.h, N, _ptr(Q), _ptr(x), _ptr(field), _ptr(energy),
+                                          m, k, _ptr(choices), _ptr(subsol), _ptr(acc),
+                                          _stream()))
+    return acc

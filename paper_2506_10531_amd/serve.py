@@ -94,3 +94,38 @@ class SolveQueue:
         st = _lib.QueueStats()
         _lib.check(_lib.load().qaoa_queue_get_stats(self.h, ctypes.byref(st)))
         return {f: getattr(st, f) for f, _ in st._fields_}
+
+    def dqaoa_cycle(self, Q, x, gamma0, beta0, m: int, k: int, *, mode="ifd", stride=1,
+                    choices=None, seed: int = 0):
+        """One DQAOA cycle (qaoa_dqaoa_cycle) on this queue: decomposition of
+        Q [N, N] (GPU float64) around the global solution x (GPU uint8 [N],
+        updated in place), m sub-QUBO solves of k qubits, aggregation.
+        mode "ifd" (windows from impact factors) or "given" (choices [m, k]
+        int32 on the GPU, e.g. random windows).  Returns (field, energy,
+        stats dict)."""
+        import torch
+        from .api import _dev, _ptr, _stream
+        Q = _dev(Q, "Q")
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.uint8
+                and x.is_contiguous()):
+            raise TypeError("x must be a contiguous uint8 GPU tensor (updated in place)")
+        N = Q.shape[0]
+        L = _lib.load()
+        md = _lib.QAOA_DECOMP_IFD if mode == "ifd" else _lib.QAOA_DECOMP_GIVEN
+        ch = None
+        if md == _lib.QAOA_DECOMP_GIVEN:
+            ch = _dev(choices, "choices", torch.int32)
+        g = np.ascontiguousarray(gamma0, dtype=np.float64).ravel()
+        b = np.ascontiguousarray(beta0, dtype=np.float64).ravel()
+        assert g.size == self.p and b.size == self.p
+        field = torch.empty(N, dtype=torch.float64, device=Q.device)
+        energy = torch.empty(1, dtype=torch.float64, device=Q.device)
+        ws = L.qaoa_cycle_workspace(N, m, k)
+        work = torch.empty(max(int(ws), 1), dtype=torch.uint8, device=Q.device)
+        st = _lib.CycleStats()
+        _lib.check(L.qaoa_dqaoa_cycle(
+            self.ctx.h, self.h, N, _ptr(Q), _ptr(x), _ptr(field), _ptr(energy), md, m, k,
+            stride, _ptr(ch), g.ctypes.data_as(ctypes.c_void_p),
+            b.ctypes.data_as(ctypes.c_void_p), int(seed) & (2**64 - 1), _ptr(work),
+            ctypes.byref(st), _stream()))
+        return field, energy, {f: getattr(st, f) for f, _ in st._fields_}

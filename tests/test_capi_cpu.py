@@ -144,3 +144,60 @@ def test_package_imports_without_gpu():
     h = api.host_context()
     info = h.plan("c64", 1, 24, 4)
     assert info["passes"] == 5
+
+
+# ---- DQAOA outer cycle entry points ----------------------------------------
+
+def _P(x):
+    return ctypes.c_void_p(0x1000) if x else None  # never dereferenced
+
+
+def test_cycle_workspace_sizes():
+    L = _lib.load()
+    assert L.qaoa_cycle_workspace(1000, 160, 20) >= 160 * 20 * 20 * 8 + 1000 * 12
+    for args in ((0, 1, 1), (70000, 1, 1), (10, 0, 1), (10, 1, 0), (10, 1, 65)):
+        assert L.qaoa_cycle_workspace(*args) == 0
+
+
+@pytest.mark.parametrize("N,nulls,rc", [
+    (100, (), _lib.ERR_NO_DEVICE), (0, (), _lib.ERR_INVALID_ARG),
+    (70000, (), _lib.ERR_INVALID_ARG), (100, (0,), _lib.ERR_INVALID_ARG),
+    (100, (1,), _lib.ERR_INVALID_ARG), (100, (2,), _lib.ERR_INVALID_ARG),
+    (100, (3,), _lib.ERR_INVALID_ARG)])
+def test_impact_arguments(hctx, N, nulls, rc):
+    a = [_P(i not in nulls) for i in range(4)]
+    assert _lib.load().qaoa_impact(hctx, N, a[0], a[1], a[2], a[3], None, None, None) == rc
+
+
+@pytest.mark.parametrize("N,m,k,stride,rc", [
+    (100, 10, 20, 1, _lib.ERR_NO_DEVICE), (100, 0, 20, 1, _lib.ERR_INVALID_ARG),
+    (100, 10, 0, 1, _lib.ERR_INVALID_ARG), (100, 10, 65, 1, _lib.ERR_INVALID_ARG),
+    (10, 10, 11, 1, _lib.ERR_INVALID_ARG), (100, 10, 20, 0, _lib.ERR_INVALID_ARG)])
+def test_windows_decompose_aggregate_arguments(hctx, N, m, k, stride, rc):
+    L = _lib.load()
+    assert L.qaoa_ifd_choices(hctx, N, _P(1), m, k, stride, _P(1), None) == rc
+    rc2 = _lib.ERR_NO_DEVICE if rc == _lib.ERR_NO_DEVICE or stride == 0 else rc
+    assert L.qaoa_decompose(hctx, N, _P(1), m, k, _P(1), _P(1), None) == rc2
+    assert L.qaoa_aggregate(hctx, N, _P(1), _P(1), _P(1), _P(1), m, k, _P(1), _P(1), None,
+                            None) == rc2
+    assert L.qaoa_decompose(hctx, N, None, m, k, _P(1), _P(1), None) == _lib.ERR_INVALID_ARG
+    assert L.qaoa_aggregate(hctx, N, _P(1), _P(1), None, _P(1), m, k, _P(1), _P(1), None,
+                            None) == _lib.ERR_INVALID_ARG
+
+
+def test_dqaoa_cycle_arguments(hctx):
+    L = _lib.load()
+    st = _lib.CycleStats()
+
+    def call(mode=_lib.QAOA_DECOMP_IFD, k=20, stride=1, ch=0, q=1, work=1):
+        return L.qaoa_dqaoa_cycle(hctx, _P(q), 100, _P(1), _P(1), _P(1), _P(1), mode, 10, k,
+                                  stride, _P(ch), _P(1), _P(1), 0, _P(work),
+                                  ctypes.byref(st), None)
+    assert call() == _lib.ERR_NO_DEVICE
+    assert call(mode=5) == _lib.ERR_INVALID_ARG
+    assert call(mode=_lib.QAOA_DECOMP_GIVEN) == _lib.ERR_INVALID_ARG   # no choices
+    assert call(mode=_lib.QAOA_DECOMP_GIVEN, ch=1) == _lib.ERR_NO_DEVICE
+    assert call(stride=0) == _lib.ERR_INVALID_ARG
+    assert call(k=23) == _lib.ERR_INVALID_ARG                          # beyond the queue
+    assert call(q=0) == _lib.ERR_INVALID_ARG
+    assert call(work=0) == _lib.ERR_INVALID_ARG

@@ -1,0 +1,192 @@
+"""The DQAOA outer cycle on the GPU (impact factors, IFD windows, sub-QUBO
+gather, aggregation, and the queue-driven cycle) against the outer-cycle
+oracle (oracle/cycle.py).
+
+Tolerances: impact factors, fields and energies are FP64 sums in another
+order than the oracle's full energy differences: |d| <= 1e-9 * max(1, sum
+|Q|).  Integer results are exact: the ranking equals the oracle's ranking
+rule applied to the GPU's own impact values (the decision taken in the same
+precision), windows and sub-QUBOs are bitwise equal, and every aggregation
+decision agrees with the oracle's full-energy difference on the same
+current solution unless that difference is within the tolerance."""
+import numpy as np
+import pytest
+
+from oracle import cycle
+from paper_2506_10531_amd import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2506_10531_amd import api as a
+    return a
+
+
+def cuda(a, dt=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda:0").to(dt)
+
+
+def problem(N, seed, symmetric=True):
+    if symmetric:
+        Q = workloads.qubo(N, seed)
+    else:
+        Q = np.random.default_rng(seed).uniform(-1, 1, (N, N))
+    x = np.random.default_rng(seed + 1).integers(0, 2, N).astype(np.uint8)
+    return Q, x
+
+
+def tol(Q):
+    return 1e-9 * max(1.0, float(np.abs(Q).sum()))
+
+
+@pytest.mark.parametrize("N,sym", [(1, True), (2, False), (7, True), (300, False),
+                                   (1000, True), (1300, False)])
+def test_impact_field_energy_order(api, N, sym):
+    Q, x = problem(N, 100 + N, sym)
+    print(f"impact N={N}", flush=True)
+    imp, field, order, e = api.impact(cuda(Q), cuda(x, torch.uint8))
+    imp, field, order, e = (t.cpu().numpy() for t in (imp, field, order, e))
+    io = cycle.impact(Q, x)
+    assert np.max(np.abs(imp - io)) <= tol(Q)
+    # the field recovered from the oracle's impact factors
+    d = 1.0 - 2.0 * x
+    g = d * io - np.diag(Q) + 2.0 * np.diag(Q) * x
+    assert np.max(np.abs(field - g)) <= tol(Q)
+    assert abs(e[0] - cycle.energy(Q, x)) <= tol(Q)
+    assert np.array_equal(np.sort(order), np.arange(N))
+    assert np.array_equal(order, cycle.rank(imp))
+
+
+def test_rank_ties_and_nan(api):
+    # exact ties resolve to the smaller index; NaN ranks last
+    Q = np.diag([1.0, -1.0, 2.0, -2.0, 0.0, 1.0])
+    x = np.zeros(6, dtype=np.uint8)
+    _, _, order, _ = api.impact(cuda(Q), cuda(x, torch.uint8))
+    assert order.cpu().numpy().tolist() == [2, 3, 0, 1, 5, 4]
+    Q[4, 4] = np.nan
+    _, _, order, _ = api.impact(cuda(Q), cuda(x, torch.uint8))
+    assert order.cpu().numpy().tolist() == [2, 3, 0, 1, 5, 4]
+    Q[4, 4] = 0.0
+    Q[0, 0] = np.nan
+    _, _, order, _ = api.impact(cuda(Q), cuda(x, torch.uint8))
+    assert order.cpu().numpy().tolist() == [2, 3, 1, 5, 4, 0]
+
+
+@pytest.mark.parametrize("N,m,k,stride", [(10, 3, 4, 1), (10, 7, 10, 3), (1000, 160, 20, 1),
+                                          (300, 40, 22, 22), (64, 5, 64, 7), (1, 2, 1, 1)])
+def test_ifd_windows(api, N, m, k, stride):
+    order = np.random.default_rng(N + m).permutation(N).astype(np.int32)
+    ch = api.ifd_choices(cuda(order, torch.int32), m, k, stride).cpu().numpy()
+    assert np.array_equal(ch, cycle.ifd_choices(order, m, k, stride))
+
+
+@pytest.mark.parametrize("N,m,k", [(1000, 160, 20), (50, 3, 50), (9, 4, 1)])
+def test_decompose_bitwise(api, N, m, k):
+    Q, _ = problem(N, 7, symmetric=False)
+    rng = np.random.default_rng(11)
+    ch = np.stack([np.sort(rng.choice(N, size=k, replace=False)) for _ in range(m)]).astype(np.int32)
+    sq = api.decompose(cuda(Q), cuda(ch, torch.int32)).cpu().numpy()
+    assert np.array_equal(sq, cycle.subqubos(Q, ch))
+
+
+def test_decompose_bad_index_gives_nan(api):
+    Q, _ = problem(12, 8)
+    ch = np.array([[0, 3, 12], [1, 2, 5]], dtype=np.int32)
+    sq = api.decompose(cuda(Q), cuda(ch, torch.int32)).cpu().numpy()
+    assert np.isnan(sq[0][2]).all() and np.isnan(sq[0][:, 2]).all()
+    assert np.array_equal(sq[0][:2, :2], Q[np.ix_([0, 3], [0, 3])])
+    assert np.array_equal(sq[1], Q[np.ix_([1, 2, 5], [1, 2, 5])])
+
+
+def _replay(Q, x0, ch, sub, acc, T):
+    """Check the GPU's decisions against the oracle's full-energy change on
+    the same current solution; returns the replayed solution."""
+    x = x0.copy()
+    e = cycle.energy(Q, x)
+    for t in range(len(ch)):
+        if acc[t] < 0:
+            continue
+        y = x.copy()
+        y[ch[t]] = (int(sub[t]) >> np.arange(ch.shape[1])) & 1
+        de = cycle.energy(Q, y) - e
+        if abs(de) > T:
+            assert bool(acc[t]) == (de < 0), (t, de, acc[t])
+        if acc[t]:
+            x, e = y, e + de
+    return x
+
+
+@pytest.mark.parametrize("N,m,k,sym", [(1000, 160, 20, True), (37, 5, 37, False),
+                                       (200, 300, 8, False)])
+def test_aggregate_against_oracle(api, N, m, k, sym):
+    Q, x0 = problem(N, 200 + N, sym)
+    rng = np.random.default_rng(N)
+    ch = np.stack([np.sort(rng.choice(N, size=k, replace=False)) for _ in range(m)]).astype(np.int32)
+    sub = rng.integers(0, 1 << k, m, dtype=np.uint64) if k < 64 else rng.integers(0, 2**63, m)
+    print(f"aggregate N={N} m={m} k={k}", flush=True)
+    Qd, xd = cuda(Q), cuda(x0, torch.uint8)
+    _, field, _, e = api.impact(Qd, xd)
+    acc = api.aggregate(Qd, xd, field, e, cuda(ch, torch.int32),
+                        torch.as_tensor(sub.astype(np.int64), device="cuda:0")).cpu().numpy()
+    xf = xd.cpu().numpy()
+    assert set(np.unique(acc)) <= {0, 1}
+    xr = _replay(Q, x0, ch, sub, acc, tol(Q))
+    assert np.array_equal(xf, xr)
+    xo, eo, acco = cycle.aggregate(Q, x0, ch, sub)
+    assert np.array_equal(xf, xo) and np.array_equal(acc.astype(bool), acco)
+    assert abs(e.item() - eo) <= tol(Q)
+    # the kept field is (Q + Q^T) x of the final solution
+    assert np.max(np.abs(field.cpu().numpy() - (Q + Q.T) @ xf.astype(np.float64))) <= tol(Q)
+
+
+def test_aggregate_skips_bad_windows(api):
+    Q, x0 = problem(20, 5)
+    ch = np.array([[0, 1, 20], [2, 3, 4]], dtype=np.int32)
+    sub = np.array([7, 5], dtype=np.int64)
+    Qd, xd = cuda(Q), cuda(x0, torch.uint8)
+    _, field, _, e = api.impact(Qd, xd)
+    acc = api.aggregate(Qd, xd, field, e, cuda(ch, torch.int32),
+                        torch.as_tensor(sub, device="cuda:0")).cpu().numpy()
+    assert acc[0] == -1
+    xo, eo, acco = cycle.aggregate(Q, x0, ch[1:], sub[1:].astype(np.uint64))
+    assert np.array_equal(xd.cpu().numpy(), xo) and bool(acc[1]) == bool(acco[0])
+
+
+@pytest.mark.parametrize("mode", ["ifd", "given"])
+def test_dqaoa_cycle_replays_through_the_oracle(api, mode):
+    """One cycle through the queue; the same sub-QUBOs solved again on a
+    separate queue (results are independent of the batch) and aggregated by
+    the oracle give the same global solution."""
+    from paper_2506_10531_amd import serve
+    N, m, k, p = 120, 12, 10, 2
+    Q, x0 = problem(N, 77)
+    g0, b0 = workloads.params(1, p, 78)
+    g0, b0 = g0[0], b0[0]
+    rng = np.random.default_rng(5)
+    given = np.stack([np.sort(rng.choice(N, size=k, replace=False)) for _ in range(m)]).astype(np.int32)
+    Qd, xd = cuda(Q), cuda(x0, torch.uint8)
+    kw = dict(prec="c64", p=p, evals=8, shots=128)
+    print(f"dqaoa cycle {mode}", flush=True)
+    with serve.SolveQueue(max_slots=8, **kw) as q:
+        field, e, st = q.dqaoa_cycle(Qd, xd, g0, b0, m, k, mode=mode, stride=1,
+                                     choices=cuda(given, torch.int32), seed=900)
+    xf = xd.cpu().numpy()
+    assert abs(st["energy"] - cycle.energy(Q, xf)) <= tol(Q)
+    assert st["energy"] <= cycle.energy(Q, x0) + tol(Q)
+    if mode == "ifd":
+        _, _, order, _ = api.impact(Qd, cuda(x0, torch.uint8))
+        ch = cycle.ifd_choices(order.cpu().numpy(), m, k, 1)
+    else:
+        ch = given
+    sq = cycle.subqubos(Q, ch)
+    with serve.SolveQueue(max_slots=1, **kw) as q:
+        ts = [q.submit(sq[t], g0, b0, 900 + t) for t in range(m)]
+        best = np.array([q.wait(t, timeout_s=120)["best_z"] for t in ts], dtype=np.uint64)
+    xo, eo, acc = cycle.aggregate(Q, x0, ch, best)
+    assert np.array_equal(xf, xo)
+    assert st["accepted"] == int(acc.sum())
+    assert abs(e.item() - eo) <= tol(Q)
