@@ -82,6 +82,8 @@ def parse():
                     help="requests of the same trace replayed against the one-at-a-time "
                          "queue (-1: all of them)")
     ap.add_argument("--serving-slots", type=int, default=256)
+    ap.add_argument("--dqaoa-cycles", type=int, default=2,
+                    help="DQAOA outer cycles on the N=1000 QUBO (0: skip)")
     ap.add_argument("--large-steps", type=int, default=3,
                     help="steps of the n=32 large-state workload (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -230,6 +232,63 @@ def large_state_leg(steps: int):
         "frac": achieved / PEAK_HBM_GBPS,
         "expect": [float(x) for x in en],
     }
+
+
+def dqaoa_leg(cycles: int, no_cpu: bool):
+    """DQAOA outer cycles (Sec. V) on one dense N = 1000 QUBO with the
+    paper's sub-QUBO count and size (160 windows of 20 variables, IFD
+    windows with stride 1): impact factors, windows and the sub-QUBO gather,
+    160 solves on the solve queue (p = 3, 100 Adam evaluations, 1024 shots,
+    complex64), aggregation.  Beside it, the oracle's classical steps (full
+    energy evaluations, as the paper's complexity counts them) on the host
+    for the first cycle's inputs."""
+    import numpy as np
+    import torch
+
+    from paper_2506_10531_amd import serve, workloads
+
+    N, m, k, p = 1000, 160, 20, 3
+    Qh = workloads.qubo(N, 3)
+    x0 = np.random.default_rng(21).integers(0, 2, N).astype(np.uint8)
+    g0, b0 = workloads.params(1, p, 22)
+    Q = torch.as_tensor(Qh, device="cuda:0")
+    x = torch.as_tensor(x0, device="cuda:0")
+    rows = []
+    with serve.SolveQueue(prec="c64", p=p, evals=100, shots=1024, max_slots=256) as q:
+        for c in range(cycles):
+            _, e, st = q.dqaoa_cycle(Q, x, g0[0], b0[0], m, k, mode="ifd", stride=1,
+                                     seed=1000 * c)
+            rows.append(st)
+    out = {
+        "workload": "dqaoa_n1000: one dense N=1000 QUBO, 160 IFD windows of 20 variables, "
+                    "p=3, 100 Adam evaluations + 1024 shots per sub-QUBO, complex64",
+        "cycles": rows,
+        "ms_per_cycle": float(np.mean([r["decompose_ms"] + r["solve_ms"] + r["aggregate_ms"]
+                                       for r in rows])),
+        "solves_per_s": m / (np.mean([r["solve_ms"] for r in rows]) * 1e-3),
+    }
+    if not no_cpu:
+        from oracle import cycle
+        t0 = time.perf_counter()
+        imp = cycle.impact(Qh, x0)
+        ch = cycle.ifd_choices(cycle.rank(imp), m, k, 1)
+        cycle.subqubos(Qh, ch)
+        t1 = time.perf_counter()
+        sub = np.random.default_rng(23).integers(0, 1 << k, m, dtype=np.uint64)
+        cycle.aggregate(Qh, x0, ch, sub)
+        t2 = time.perf_counter()
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([d.get("num_threads", 1) for d in threadpool_info()
+                         if d.get("user_api") == "blas"] or [1])
+        except Exception:  # noqa: BLE001 - the count is informational
+            cores = None
+        out["cpu_oracle_classical_steps"] = {
+            "decompose_ms": 1e3 * (t1 - t0), "aggregate_ms": 1e3 * (t2 - t1),
+            "cores": cores, "kind": "oracle",
+            "sample": "impact factors by N full energy evaluations, IFD windows, sub-QUBOs; "
+                      "aggregation of 160 random sub-solutions by full energy evaluations"}
+    return out
 
 
 def main():
@@ -400,6 +459,8 @@ def main():
                                      calib=min(256, args.serving_requests))
     if args.large_steps > 0:
         out["large_state"] = large_state_leg(args.large_steps)
+    if args.dqaoa_cycles > 0:
+        out["dqaoa"] = dqaoa_leg(args.dqaoa_cycles, args.no_cpu_baseline)
     print(json.dumps(out))
 
 
