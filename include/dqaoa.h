@@ -250,6 +250,17 @@ int qaoa_wait(qaoa_queue* q, uint64_t ticket, int64_t timeout_ns,
 int qaoa_cancel(qaoa_queue* q, uint64_t ticket);
 int qaoa_queue_get_stats(qaoa_queue* q, qaoa_queue_stats* out);
 
+/* Sampled objective of a sampler-based QAOA (the measurement of Sec. IV):
+ * out[b] = CVaR_alpha of the shot energies cz[b][0..shots) (device, FP64,
+ * e.g. from qaoa_sample), the mean over the lowest alpha fraction of the
+ * empirical distribution with the boundary shot weighted fractionally:
+ *   ( sum_{k <= floor(a)} E_(k) + (a - floor(a)) E_(floor(a)+1) ) / a,
+ *   a = alpha * shots, E_(1) <= ... <= E_(shots);
+ * alpha = 1 is the shot mean.  1 <= B <= 65535, 1 <= shots <= 65536,
+ * 0 < alpha <= 1. */
+int qaoa_cvar(qaoa_ctx* ctx, int B, int shots, const double* cz, double alpha,
+              double* out, qaoa_stream_t stream);
+
 /* ---- DQAOA outer cycle (Sec. V) ------------------------------------------
  * The classical steps around the sub-QUBO solves, on the device, for one
  * dense N x N QUBO Q (device, row-major FP64) and a global 0/1 solution x

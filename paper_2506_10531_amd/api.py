@@ -292,3 +292,24 @@ def aggregate(Q, x, field, energy, choices, subsol, ctx=None):
                                           m, k, _ptr(choices), _ptr(subsol), _ptr(acc),
                                           _stream()))
     return acc
+
+
+def cvar(cz, alpha: float = 1.0, ctx=None):
+    """CVaR_alpha [B] of shot energies cz [B, shots] (qaoa_cvar); alpha = 1
+    is the shot mean."""
+    cz = _dev(cz, "cz")
+    if cz.dim() == 1:
+        cz = cz.unsqueeze(0)
+    B, K = cz.shape
+    ctx = ctx or default_context(cz.device.index)
+    out = torch.empty(B, dtype=torch.float64, device=cz.device)
+    _lib.check(_lib.load().qaoa_cvar(ctx.h, B, K, _ptr(cz), float(alpha), _ptr(out), _stream()))
+    return out
+
+
+def sampled_objective(Q, gammas, betas, shots: int, seed: int, alpha: float = 1.0, prec="c64",
+                      ctx=None):
+    """The objective of a sampler-based QAOA: CVaR_alpha [B] of the energies
+    of `shots` samples per problem (qaoa_sample, then qaoa_cvar)."""
+    s = sample(Q, gammas, betas, shots, seed, prec=prec, ctx=ctx)
+    return cvar(s["cz"], alpha, ctx=ctx)

@@ -201,3 +201,11 @@ def test_dqaoa_cycle_arguments(hctx):
     assert call(k=23) == _lib.ERR_INVALID_ARG                          # beyond the queue
     assert call(q=0) == _lib.ERR_INVALID_ARG
     assert call(work=0) == _lib.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("B,shots,alpha,ok", [
+    (4, 1024, 0.25, True), (0, 10, 1.0, False), (70000, 10, 1.0, False), (1, 0, 1.0, False),
+    (1, 70000, 1.0, False), (1, 10, 0.0, False), (1, 10, 1.5, False), (1, 10, float("nan"), False)])
+def test_cvar_arguments(hctx, B, shots, alpha, ok):
+    rc = _lib.load().qaoa_cvar(hctx, B, shots, _P(1), alpha, _P(1), None)
+    assert rc == (_lib.ERR_NO_DEVICE if ok else _lib.ERR_INVALID_ARG)
