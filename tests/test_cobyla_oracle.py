@@ -1,27 +1,45 @@
-"""Pins of the oracle's COBYLA loop (oracle/cobyla_loop.py) by cases whose
-optimum is known without it: a one-variable QUBO, whose p = 1 objective is
-q times the probability of z = 1 (minimum min(0, q)); a dense grid of the
-two-variable objective, which COBYLA started at the best grid point may only
-refine; and descent from a random start."""
+"""Pins of the oracle's COBYLA-type loop (oracle/cobyla_loop.py) by cases
+whose optimum is known without it: a one-variable QUBO, whose p = 1
+objective is q times the probability of z = 1 (minimum min(0, q)); convex
+quadratics with a known minimiser, where SciPy's COBYLA (Powell's reference
+code) reaches the same minimum; refinement of a dense objective grid; and
+the evaluation budget."""
 import numpy as np
 import pytest
+from scipy.optimize import minimize
 
-from oracle.cobyla_loop import cobyla_loop
+from oracle import expect
+from oracle.cobyla_loop import cobyla_loop, cobyla_min
 
 
 @pytest.mark.parametrize("q", [1.5, -0.7])
 def test_one_variable_reaches_min_zero_q(q):
     Q = np.array([[q]])
-    th, f, nfev = cobyla_loop(Q, np.array([0.4, 0.3]), maxiter=400, tol=1e-10)
+    th, f, nfev = cobyla_loop(Q, np.array([0.4, 0.3]), rhoend=1e-8, maxfun=500)
     assert abs(f - min(0.0, q)) <= 1e-6 * abs(q)
-    assert nfev > 2
+    assert 3 <= nfev <= 500
+
+
+@pytest.mark.parametrize("n,seed", [(2, 1), (4, 2), (6, 3)])
+def test_convex_quadratic_minimiser_and_reference(n, seed):
+    rng = np.random.default_rng(seed)
+    M = rng.normal(size=(n, n))
+    H = M @ M.T + 0.5 * np.eye(n)
+    c = rng.normal(size=n)
+
+    def f(x):
+        r = x - c
+        return float(r @ H @ r) - 2.0
+
+    x, fx, nfev = cobyla_min(f, np.zeros(n), rhobeg=0.5, rhoend=1e-7, maxfun=5000)
+    assert np.max(np.abs(x - c)) <= 1e-3
+    assert fx + 2.0 <= 1e-6
+    ref = minimize(f, np.zeros(n), method="COBYLA",
+                   options=dict(rhobeg=0.5, tol=1e-7, maxiter=5000))
+    assert abs(fx - ref.fun) <= 1e-6
 
 
 def test_refines_a_grid_minimum():
-    # a dense grid of the objective (the exact n = 2 expectation, p = 1),
-    # then COBYLA from the best grid point: it may only improve on it, and
-    # by no more than the grid spacing allows
-    from oracle import expect
     Q = np.array([[0.3, -0.8], [-0.8, 0.6]])
     gs = np.linspace(0, 2 * np.pi, 181)
     bs = np.linspace(0, np.pi, 91)
@@ -29,17 +47,18 @@ def test_refines_a_grid_minimum():
     e = expect(Q, G.reshape(-1, 1), Bt.reshape(-1, 1))[0]
     k = int(np.argmin(e))
     th, f, _ = cobyla_loop(Q, np.array([G.ravel()[k], Bt.ravel()[k]]), rhobeg=0.02,
-                           maxiter=400, tol=1e-10)
+                           rhoend=1e-8, maxfun=400)
     assert f <= e[k] + 1e-12
-    assert e[k] - f <= 0.05 * (np.abs(Q).sum())
+    assert e[k] - f <= 0.05 * np.abs(Q).sum()
 
 
-def test_never_worse_than_start():
+def test_budget_and_descent():
     rng = np.random.default_rng(4)
     Q = rng.uniform(-1, 1, (5, 5))
     Q = np.triu(Q) + np.triu(Q, 1).T
     th0 = np.array([0.3, 0.9])
-    from oracle import expect
     e0 = expect(Q, th0[None, :1], th0[None, 1:])[0][0]
-    _, f, _ = cobyla_loop(Q, th0, maxiter=100)
-    assert f <= e0
+    _, f, nfev = cobyla_loop(Q, th0, maxfun=7)
+    assert nfev == 7 and f <= e0
+    _, f, nfev = cobyla_loop(Q, th0, maxfun=300)
+    assert f <= e0 and nfev <= 300
