@@ -82,6 +82,8 @@ def parse():
                     help="requests of the same trace replayed against the one-at-a-time "
                          "queue (-1: all of them)")
     ap.add_argument("--serving-slots", type=int, default=256)
+    ap.add_argument("--cobyla-subqubos", type=int, default=64,
+                    help="sub-QUBOs of the COBYLA (p=1) versus device-Adam leg (0: skip)")
     ap.add_argument("--dqaoa-cycles", type=int, default=2,
                     help="DQAOA outer cycles on the N=1000 QUBO (0: skip)")
     ap.add_argument("--large-steps", type=int, default=3,
@@ -291,6 +293,47 @@ def dqaoa_leg(cycles: int, no_cpu: bool):
     return out
 
 
+def cobyla_leg(count: int):
+    """The paper's variational loop (COBYLA-type steps from random
+    parameters, p = 1; qaoa_cobyla batches every round of requests into one
+    qaoa_expect) on `count` 20-variable sub-QUBOs of the N = 1000 QUBO,
+    beside the solve queue's device Adam (100 evaluations) from the same
+    initial parameters; both sampled with 1024 shots, complex64."""
+    import numpy as np
+    import torch
+
+    from paper_2506_10531_amd import api, serve, workloads
+
+    _, rs = workloads.subqubo_requests(count, N=1000, n_lo=20, n_hi=20, seed=3)
+    Qs = np.stack([Q for _, Q in rs])
+    g, b = workloads.params(count, 1, 24)
+    th0 = np.concatenate([g, b], axis=1)
+    Qd = torch.as_tensor(Qs, device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = api.cobyla(Qd, th0, rhobeg=0.5, rhoend=1e-4, maxfun=100, prec="c64")
+    s = api.sample(Qd, torch.as_tensor(r["theta"][:, :1], device="cuda:0"),
+                   torch.as_tensor(r["theta"][:, 1:], device="cuda:0"), 1024, 5, prec="c64")
+    bc = s["best_c"].cpu().numpy()
+    tc = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    with serve.SolveQueue(prec="c64", p=1, evals=100, shots=1024, max_slots=count) as q:
+        ts = [q.submit(Qs[i], g[i], b[i], 5 + i) for i in range(count)]
+        res = [q.wait(t, timeout_s=300) for t in ts]
+    ta = time.perf_counter() - t0
+    return {
+        "workload": f"{count} sub-QUBOs of n=20 from the N=1000 QUBO, p=1, random initial "
+                    "parameters, 1024 shots, complex64",
+        "cobyla": {"solves_per_s": count / tc, "mean_expect": float(np.mean(r["expect"])),
+                   "mean_best_c": float(np.mean(bc)),
+                   "mean_evaluations": float(np.mean(r["nfev"])),
+                   "batched_rounds": int(r["rounds"]), "rhoend": 1e-4, "maxfun": 100},
+        "device_adam_100": {"solves_per_s": count / ta,
+                            "mean_expect": float(np.mean([x["expect"] for x in res])),
+                            "mean_best_c": float(np.mean([x["best_c"] for x in res]))},
+    }
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -461,6 +504,8 @@ def main():
         out["large_state"] = large_state_leg(args.large_steps)
     if args.dqaoa_cycles > 0:
         out["dqaoa"] = dqaoa_leg(args.dqaoa_cycles, args.no_cpu_baseline)
+    if args.cobyla_subqubos > 0:
+        out["cobyla_p1"] = cobyla_leg(args.cobyla_subqubos)
     print(json.dumps(out))
 
 

@@ -250,6 +250,25 @@ int qaoa_wait(qaoa_queue* q, uint64_t ticket, int64_t timeout_ns,
 int qaoa_cancel(qaoa_queue* q, uint64_t ticket);
 int qaoa_queue_get_stats(qaoa_queue* q, qaoa_queue_stats* out);
 
+/* COBYLA-type optimisation of the QAOA parameters (Sec. IV: the paper's
+ * variational loop, COBYLA from random values, there at p = 1) for B
+ * independent problems Q (device [B][n][n]), problem b starting from
+ * theta0[b] = (gamma_1..p, beta_1..p) (host [B][2p]) and minimising <C>
+ * (Eq. (1)).  The unconstrained COBYLA steps: a simplex of 2p + 1 points,
+ * the trust step to the minimiser of their linear interpolant within radius
+ * rho, geometry steps that keep the simplex well shaped, rho halved from
+ * rhobeg down to rhoend when the model predicts poorly; at most maxfun
+ * evaluations per problem.  Every round, the points of all running
+ * optimisers are evaluated by one qaoa_expect call.  Outputs (host): theta
+ * [B][2p] the best point, expect [B] <C> there, nfev [B] evaluations
+ * (nullable), rounds [1] batched calls (nullable).  Requires rhobeg >=
+ * rhoend > 0, maxfun >= 1.  Blocking (synchronises stream); allocates its
+ * device buffers for the call. */
+int qaoa_cobyla(qaoa_ctx* ctx, int prec, int B, int n, int p, const double* Q,
+                const double* theta0, double rhobeg, double rhoend, int maxfun,
+                double* theta, double* expect, int* nfev, int* rounds,
+                qaoa_stream_t stream);
+
 /* Sampled objective of a sampler-based QAOA (the measurement of Sec. IV):
  * out[b] = CVaR_alpha of the shot energies cz[b][0..shots) (device, FP64,
  * e.g. from qaoa_sample), the mean over the lowest alpha fraction of the

@@ -42,7 +42,7 @@ EXPORTS = [
     "qaoa_queue_destroy", "qaoa_submit", "qaoa_poll", "qaoa_wait",
     "qaoa_cancel", "qaoa_queue_get_stats",
     "qaoa_impact", "qaoa_ifd_choices", "qaoa_decompose", "qaoa_aggregate",
-    "qaoa_cycle_workspace", "qaoa_dqaoa_cycle", "qaoa_cvar",
+    "qaoa_cycle_workspace", "qaoa_dqaoa_cycle", "qaoa_cvar", "qaoa_cobyla",
 ]
 
 QAOA_DECOMP_GIVEN = 0
@@ -145,6 +145,8 @@ def load():
     L.qaoa_aggregate.argtypes = [vp, i, dp, dp, dp, dp, i, i, dp, dp, dp, vp]
     L.qaoa_cycle_workspace.argtypes = [i, i, i]
     L.qaoa_cvar.argtypes = [vp, i, i, dp, ctypes.c_double, dp, vp]
+    L.qaoa_cobyla.argtypes = [vp, i, i, i, i, dp, dp, ctypes.c_double, ctypes.c_double, i,
+                              dp, dp, dp, dp, vp]
     L.qaoa_dqaoa_cycle.argtypes = [vp, vp, i, dp, dp, dp, dp, i, i, i, i, dp, dp, dp,
                                    u64, dp, ctypes.POINTER(CycleStats), vp]
     for name in EXPORTS:

@@ -313,3 +313,31 @@ def sampled_objective(Q, gammas, betas, shots: int, seed: int, alpha: float = 1.
     of `shots` samples per problem (qaoa_sample, then qaoa_cvar)."""
     s = sample(Q, gammas, betas, shots, seed, prec=prec, ctx=ctx)
     return cvar(s["cz"], alpha, ctx=ctx)
+
+
+def cobyla(Q, theta0, rhobeg: float = 0.5, rhoend: float = 1e-6, maxfun: int = 200,
+           prec="c128", ctx=None):
+    """COBYLA-type minimisation of <C> over (gamma, beta) for every problem
+    Q [B, n, n] (GPU float64) from theta0 [B, 2p] (host array), batched:
+    every round of requests is one qaoa_expect (qaoa_cobyla).  Returns
+    dict(theta [B, 2p], expect [B], nfev [B], rounds)."""
+    import numpy as np
+    Q = _dev(Q, "Q")
+    if Q.dim() == 2:
+        Q = Q.unsqueeze(0)
+    B, n, _ = Q.shape
+    th0 = np.ascontiguousarray(theta0, dtype=np.float64).reshape(B, -1)
+    if th0.shape[1] % 2:
+        raise ValueError("theta0 must be [B, 2p]")
+    p = th0.shape[1] // 2
+    ctx = ctx or default_context(Q.device.index)
+    th = np.empty_like(th0)
+    e = np.empty(B)
+    nf = np.empty(B, dtype=np.int32)
+    r = ctypes.c_int(0)
+    cp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    _lib.check(_lib.load().qaoa_cobyla(ctx.h, _prec(prec), B, n, p, _ptr(Q), cp(th0),
+                                       float(rhobeg), float(rhoend), int(maxfun), cp(th), cp(e),
+                                       cp(nf), ctypes.cast(ctypes.pointer(r), ctypes.c_void_p),
+                                       _stream()))
+    return dict(theta=th, expect=e, nfev=nf, rounds=r.value)

@@ -209,3 +209,17 @@ def test_dqaoa_cycle_arguments(hctx):
 def test_cvar_arguments(hctx, B, shots, alpha, ok):
     rc = _lib.load().qaoa_cvar(hctx, B, shots, _P(1), alpha, _P(1), None)
     assert rc == (_lib.ERR_NO_DEVICE if ok else _lib.ERR_INVALID_ARG)
+
+
+def test_cobyla_arguments(hctx):
+    L = _lib.load()
+
+    def call(prec=0, B=4, n=10, p=1, rb=0.5, re=1e-6, mf=100, ptrs=(1, 1, 1, 1)):
+        q, t0, t, e = (_P(v) for v in ptrs)
+        return L.qaoa_cobyla(hctx, prec, B, n, p, q, t0, rb, re, mf, t, e, None, None, None)
+    assert call() == _lib.ERR_NO_DEVICE
+    for kw in (dict(prec=3), dict(B=0), dict(n=0), dict(n=35), dict(p=0), dict(p=65),
+               dict(rb=1e-7, re=1e-6), dict(re=0.0), dict(rb=float("inf")), dict(mf=0),
+               dict(ptrs=(0, 1, 1, 1)), dict(ptrs=(1, 0, 1, 1)), dict(ptrs=(1, 1, 0, 1)),
+               dict(ptrs=(1, 1, 1, 0))):
+        assert call(**kw) == _lib.ERR_INVALID_ARG, kw
