@@ -59,6 +59,24 @@ def subqubo_requests(count: int, N: int = 1000, n_lo: int = 12, n_hi: int = 22,
     return Qg, reqs
 
 
+def maxcut_qubo(N: int, seed: int, edges: int | None = None):
+    """Unweighted Max-Cut instance of Sec. VI-B: floor(N(N-1)/8) distinct
+    edges drawn uniformly from all node pairs (25% of a complete graph), as
+    the QUBO minimising minus the cut: Q_ii = -deg(i), Q_ij = Q_ji = 1 per
+    edge, so x^T Q x = -(number of cut edges).  Returns (Q, edges [E, 2])."""
+    rng = np.random.default_rng(seed)
+    E = N * (N - 1) // 8 if edges is None else edges
+    pairs = rng.choice(N * (N - 1) // 2, size=E, replace=False)
+    # pair index -> (i, j), i < j, in row-major order of the upper triangle
+    i = (N - 2 - np.floor(np.sqrt(-8.0 * pairs + 4.0 * N * (N - 1) - 7) / 2.0 - 0.5)).astype(np.int64)
+    j = (pairs + i + 1 - N * (N - 1) // 2 + (N - i) * ((N - i) - 1) // 2).astype(np.int64)
+    Q = np.zeros((N, N))
+    Q[i, j] = 1.0
+    Q[j, i] = 1.0
+    Q[np.arange(N), np.arange(N)] = -Q.sum(axis=1)
+    return Q, np.stack([i, j], axis=1)
+
+
 def poisson_arrivals(count: int, rate: float, seed: int) -> np.ndarray:
     """Arrival times (s) of a Poisson process of the given rate (1/s)."""
     rng = np.random.default_rng(seed)
