@@ -306,6 +306,20 @@ int qaoa_impact(qaoa_ctx* ctx, int N, const double* Q, const uint8_t* x,
 int qaoa_ifd_choices(qaoa_ctx* ctx, int N, const int32_t* order, int m, int k,
                      int stride, int32_t* choices, qaoa_stream_t stream);
 
+/* BFS / PFS windows (Sec. V-A-3), mode QAOA_DECOMP_BFS or QAOA_DECOMP_PFS:
+ * variables i, j interact when Q_ij + Q_ji != 0; window t starts at
+ * order[t mod N] and grows to k variables.  BFS expands the window's
+ * variables first-in first-out, taking each one's unselected neighbours by
+ * |Q_ij + Q_ji| (largest first); PFS takes the unselected variable of
+ * largest |impact| that interacts with the window.  With no such variable
+ * both continue from the unselected variable of largest |impact|.  Ties go
+ * to the smaller index.  choices [m][k] int32, each window sorted
+ * ascending.  impact and order as qaoa_impact writes them; N <= 16384. */
+int qaoa_traversal_choices(qaoa_ctx* ctx, int N, const double* Q,
+                           const double* impact, const int32_t* order,
+                           int mode, int m, int k, int32_t* choices,
+                           qaoa_stream_t stream);
+
 /* Sub-QUBOs (Sec. V, first step): subq[t] = Q[S_t, S_t], [m][k][k] FP64,
  * with S_t = choices[t][0..k) (ascending and distinct; bit r of a sub-QUBO
  * basis index is variable choices[t][r]).  Random decomposition (Sec.
@@ -328,7 +342,7 @@ int qaoa_aggregate(qaoa_ctx* ctx, int N, const double* Q, uint8_t* x,
 /* Bytes of device workspace qaoa_dqaoa_cycle needs (0 for invalid sizes). */
 size_t qaoa_cycle_workspace(int N, int m, int k);
 
-enum { QAOA_DECOMP_GIVEN = 0, QAOA_DECOMP_IFD = 1 };
+enum { QAOA_DECOMP_GIVEN = 0, QAOA_DECOMP_IFD = 1, QAOA_DECOMP_BFS = 2, QAOA_DECOMP_PFS = 3 };
 
 typedef struct {
   double decompose_ms;  /* impact factors, windows, sub-QUBO gather + copy */
@@ -339,8 +353,9 @@ typedef struct {
 } qaoa_cycle_stats;
 
 /* One DQAOA cycle (Sec. V): windows from the impact factors of x (mode
- * QAOA_DECOMP_IFD, with stride) or from choices (device [m][k], mode
- * QAOA_DECOMP_GIVEN, e.g. random windows); the m sub-QUBOs solved on queue
+ * QAOA_DECOMP_IFD, with stride; QAOA_DECOMP_BFS / _PFS, N <= 16384) or from
+ * choices (device [m][k], mode QAOA_DECOMP_GIVEN, e.g. random windows); the
+ * m sub-QUBOs solved on queue
  * q (k <= 22 qubits each; initial parameters gamma0/beta0 are host arrays
  * of the queue's p; request t samples with seed + t); their best samples
  * aggregated into x.  field and energy [1] (device) receive (Q + Q^T) x and

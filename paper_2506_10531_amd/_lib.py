@@ -43,10 +43,13 @@ EXPORTS = [
     "qaoa_cancel", "qaoa_queue_get_stats",
     "qaoa_impact", "qaoa_ifd_choices", "qaoa_decompose", "qaoa_aggregate",
     "qaoa_cycle_workspace", "qaoa_dqaoa_cycle", "qaoa_cvar", "qaoa_cobyla",
+    "qaoa_traversal_choices",
 ]
 
 QAOA_DECOMP_GIVEN = 0
 QAOA_DECOMP_IFD = 1
+QAOA_DECOMP_BFS = 2
+QAOA_DECOMP_PFS = 3
 
 
 class QaoaError(RuntimeError):
@@ -141,6 +144,7 @@ def load():
     L.qaoa_queue_get_stats.argtypes = [vp, ctypes.POINTER(QueueStats)]
     L.qaoa_impact.argtypes = [vp, i, dp, dp, dp, dp, dp, dp, vp]
     L.qaoa_ifd_choices.argtypes = [vp, i, dp, i, i, i, dp, vp]
+    L.qaoa_traversal_choices.argtypes = [vp, i, dp, dp, dp, i, i, i, dp, vp]
     L.qaoa_decompose.argtypes = [vp, i, dp, i, i, dp, dp, vp]
     L.qaoa_aggregate.argtypes = [vp, i, dp, dp, dp, dp, i, i, dp, dp, dp, vp]
     L.qaoa_cycle_workspace.argtypes = [i, i, i]

@@ -260,6 +260,21 @@ def ifd_choices(order, m: int, k: int, stride: int = 1, ctx=None):
     return ch
 
 
+def traversal_choices(Q, impact, order, m: int, k: int, mode: str = "pfs", ctx=None):
+    """BFS ("bfs") or PFS ("pfs") windows [m, k] int32 (qaoa_traversal_choices)
+    from impact factors and their ranking (as api.impact returns them)."""
+    Q = _dev(Q, "Q")
+    impact = _dev(impact, "impact")
+    order = _dev(order, "order", torch.int32)
+    N = Q.shape[0]
+    ctx = ctx or default_context(Q.device.index)
+    md = {"bfs": _lib.QAOA_DECOMP_BFS, "pfs": _lib.QAOA_DECOMP_PFS}[mode]
+    ch = torch.empty((m, k), dtype=torch.int32, device=Q.device)
+    _lib.check(_lib.load().qaoa_traversal_choices(ctx.h, N, _ptr(Q), _ptr(impact), _ptr(order), md,
+                                                  m, k, _ptr(ch), _stream()))
+    return ch
+
+
 def decompose(Q, choices, ctx=None):
     """Sub-QUBOs Q[S_t, S_t] [m, k, k] of the windows choices [m, k] int32."""
     Q = _dev(Q, "Q")

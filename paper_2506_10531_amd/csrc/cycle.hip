@@ -126,6 +126,114 @@ __global__ void __launch_bounds__(64) windows_kernel(int N, const int32_t* __res
   if (r < k) choices[(size_t)t * k + pos] = v;
 }
 
+// ---- BFS / PFS windows (Sec. V-A-3) -----------------------------------------
+// Variables i and j interact when W_ij = Q_ij + Q_ji != 0; window t starts at
+// order[t mod N].  BFS expands the window's variables first-in first-out and
+// takes each one's unselected neighbours by |W| (largest first, ties to the
+// smaller index); PFS takes the unselected variable of largest |impact| that
+// interacts with the window.  With no such variable both restart from the
+// unselected variable of largest |impact|.  Ties go to the smaller index
+// everywhere.  One 256-thread work-group per window; the picks are block
+// arg-max reductions over N, so a window costs O(k N).
+constexpr int TRAV_MAX_N = 16384;
+
+// (key, index) pairs: larger key first, then smaller index; key < 0 = none.
+struct Pick {
+  double key;
+  int idx;
+};
+__device__ __forceinline__ bool better(const Pick& a, const Pick& b) {
+  return a.key > b.key || (a.key == b.key && a.idx < b.idx);
+}
+__device__ Pick block_pick(Pick p, Pick* red) {
+  for (int off = 32; off > 0; off >>= 1) {
+    Pick o{__shfl_xor(p.key, off, 64), __shfl_xor(p.idx, off, 64)};
+    if (better(o, p)) p = o;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = p;
+  __syncthreads();
+  Pick b = red[0];
+  for (int w = 1; w < 4; ++w)
+    if (better(red[w], b)) b = red[w];
+  __syncthreads();
+  return b;
+}
+
+template <bool PFS>
+__global__ void __launch_bounds__(256) traverse_kernel(int N, const double* __restrict__ Q,
+                                                       const double* __restrict__ imp,
+                                                       const int32_t* __restrict__ order, int k,
+                                                       int32_t* __restrict__ choices) {
+  __shared__ uint8_t sel[TRAV_MAX_N];
+  __shared__ uint8_t front[TRAV_MAX_N];
+  __shared__ int win[MAX_K];
+  __shared__ Pick red[4];
+  const int t = blockIdx.x, tid = threadIdx.x;
+  for (int i = tid; i < N; i += 256) sel[i] = front[i] = 0;
+  if (tid < MAX_K) win[tid] = -1;  // an unfilled place stays out of range
+  __syncthreads();
+  int seed = order[t % N];
+  seed = seed < 0 || seed >= N ? 0 : seed;
+  int cnt = 0, head = 0;
+  // adds v to the window (and, for PFS, its interacting variables to the frontier)
+  auto add = [&](int v) {
+    if (tid == 0) {
+      sel[v] = 1;
+      win[cnt] = v;
+    }
+    if (PFS)
+      for (int i = tid; i < N; i += 256)
+        if (i != v && Q[(size_t)v * N + i] + Q[(size_t)i * N + v] != 0.0) front[i] = 1;
+    __syncthreads();
+    ++cnt;
+  };
+  add(seed);
+  while (cnt < k) {
+    Pick p{-1.0, 0x7fffffff};
+    if (PFS) {
+      for (int i = tid; i < N; i += 256)
+        if (front[i] && !sel[i]) {
+          const Pick c{fabs(imp[i]), i};
+          if (better(c, p)) p = c;
+        }
+      p = block_pick(p, red);
+    } else if (head < cnt) {
+      const int u = win[head];
+      for (int i = tid; i < N; i += 256) {
+        if (sel[i] || i == u) continue;
+        const double w = Q[(size_t)u * N + i] + Q[(size_t)i * N + u];
+        if (w != 0.0) {
+          const Pick c{fabs(w), i};
+          if (better(c, p)) p = c;
+        }
+      }
+      p = block_pick(p, red);
+      if (p.key < 0.0) {  // u has no unselected neighbour left
+        ++head;
+        continue;
+      }
+    }
+    if (p.key < 0.0) {  // restart: the unselected variable of largest |impact|
+      Pick r{-1.0, 0x7fffffff};
+      for (int i = tid; i < N; i += 256)
+        if (!sel[i]) {
+          const Pick c{fabs(imp[i]), i};
+          if (better(c, r)) r = c;
+        }
+      p = block_pick(r, red);
+      if (p.key < 0.0) break;  // every variable selected (k <= N makes this unreachable)
+    }
+    add(p.idx);
+  }
+  // the window sorted ascending
+  if (tid < k) {
+    const int v = win[tid];
+    int pos = 0;
+    for (int j = 0; j < k; ++j) pos += win[j] < v;
+    choices[(size_t)t * k + pos] = v;
+  }
+}
+
 // subq[t] = Q[S_t, S_t]; an index outside [0, N) makes its row and column NaN.
 __global__ void __launch_bounds__(256) gather_kernel(int N, const double* __restrict__ Q, int k,
                                                      const int32_t* __restrict__ choices,
@@ -288,6 +396,32 @@ int qaoa_ifd_choices(qaoa_ctx* ctx, int N, const int32_t* order, int m, int k, i
   return e == hipSuccess ? QAOA_OK : hip_error(e, "windows kernel");
 }
 
+int qaoa_traversal_choices(qaoa_ctx* ctx, int N, const double* Q, const double* impact,
+                           const int32_t* order, int mode, int m, int k, int32_t* choices,
+                           qaoa_stream_t stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  rc = check_nk(N, m, k);
+  if (rc) return rc;
+  if (N > TRAV_MAX_N)
+    return set_error(QAOA_ERR_INVALID_ARG, "N = %d exceeds %d for BFS/PFS windows", N, TRAV_MAX_N);
+  if (mode != QAOA_DECOMP_BFS && mode != QAOA_DECOMP_PFS)
+    return set_error(QAOA_ERR_INVALID_ARG, "mode %d is not QAOA_DECOMP_BFS or _PFS", mode);
+  if (!Q || !impact || !order || !choices)
+    return set_error(QAOA_ERR_INVALID_ARG, "Q, impact, order and choices must be non-NULL");
+  rc = check_dev(ctx);
+  if (rc) return rc;
+  Dev g(ctx_device(ctx));
+  if (mode == QAOA_DECOMP_PFS)
+    hipLaunchKernelGGL(traverse_kernel<true>, dim3(m), dim3(256), 0, (hipStream_t)stream, N, Q,
+                       impact, order, k, choices);
+  else
+    hipLaunchKernelGGL(traverse_kernel<false>, dim3(m), dim3(256), 0, (hipStream_t)stream, N, Q,
+                       impact, order, k, choices);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? QAOA_OK : hip_error(e, "traversal kernel");
+}
+
 int qaoa_decompose(qaoa_ctx* ctx, int N, const double* Q, int m, int k, const int32_t* choices,
                    double* subq, qaoa_stream_t stream) {
   int rc = check_ctx(ctx);
@@ -336,8 +470,11 @@ int qaoa_dqaoa_cycle(qaoa_ctx* ctx, qaoa_queue* q, int N, const double* Q, uint8
   if (!q || !Q || !x || !field || !energy || !gamma0 || !beta0 || !work)
     return set_error(QAOA_ERR_INVALID_ARG,
                      "q, Q, x, field, energy, gamma0, beta0 and work must be non-NULL");
-  if (mode != QAOA_DECOMP_IFD && mode != QAOA_DECOMP_GIVEN)
-    return set_error(QAOA_ERR_INVALID_ARG, "mode %d is not QAOA_DECOMP_IFD or _GIVEN", mode);
+  if (mode != QAOA_DECOMP_IFD && mode != QAOA_DECOMP_GIVEN && mode != QAOA_DECOMP_BFS &&
+      mode != QAOA_DECOMP_PFS)
+    return set_error(QAOA_ERR_INVALID_ARG, "mode %d is not a QAOA_DECOMP_* mode", mode);
+  if ((mode == QAOA_DECOMP_BFS || mode == QAOA_DECOMP_PFS) && N > TRAV_MAX_N)
+    return set_error(QAOA_ERR_INVALID_ARG, "N = %d exceeds %d for BFS/PFS windows", N, TRAV_MAX_N);
   if (mode == QAOA_DECOMP_IFD && stride < 1)
     return set_error(QAOA_ERR_INVALID_ARG, "stride = %d < 1", stride);
   if (mode == QAOA_DECOMP_GIVEN && !choices_in)
@@ -362,11 +499,17 @@ int qaoa_dqaoa_cycle(qaoa_ctx* ctx, qaoa_queue* q, int N, const double* Q, uint8
   Dev g(ctx_device(ctx));
   hipStream_t s = (hipStream_t)stream;
   const auto t0 = clk::now();
-  hipError_t e = enqueue_impact(N, Q, x, imp, field, mode == QAOA_DECOMP_IFD ? order : nullptr,
+  hipError_t e = enqueue_impact(N, Q, x, imp, field, mode == QAOA_DECOMP_GIVEN ? nullptr : order,
                                 energy, s);
   if (e != hipSuccess) return hip_error(e, "impact kernels");
   if (mode == QAOA_DECOMP_IFD) {
     hipLaunchKernelGGL(windows_kernel, dim3(m), dim3(64), 0, s, N, order, k, (long long)stride,
+                       choices);
+  } else if (mode == QAOA_DECOMP_BFS) {
+    hipLaunchKernelGGL(traverse_kernel<false>, dim3(m), dim3(256), 0, s, N, Q, imp, order, k,
+                       choices);
+  } else if (mode == QAOA_DECOMP_PFS) {
+    hipLaunchKernelGGL(traverse_kernel<true>, dim3(m), dim3(256), 0, s, N, Q, imp, order, k,
                        choices);
   } else {
     e = hipMemcpyAsync(choices, choices_in, (size_t)m * k * 4, hipMemcpyDeviceToDevice, s);

@@ -100,8 +100,8 @@ class SolveQueue:
         """One DQAOA cycle (qaoa_dqaoa_cycle) on this queue: decomposition of
         Q [N, N] (GPU float64) around the global solution x (GPU uint8 [N],
         updated in place), m sub-QUBO solves of k qubits, aggregation.
-        mode "ifd" (windows from impact factors) or "given" (choices [m, k]
-        int32 on the GPU, e.g. random windows).  Returns (field, energy,
+        mode "ifd", "bfs" or "pfs" (windows from impact factors) or "given"
+        (choices [m, k] int32 on the GPU, e.g. random windows).  Returns (field, energy,
         stats dict)."""
         import torch
         from .api import _dev, _ptr, _stream
@@ -111,7 +111,8 @@ class SolveQueue:
             raise TypeError("x must be a contiguous uint8 GPU tensor (updated in place)")
         N = Q.shape[0]
         L = _lib.load()
-        md = _lib.QAOA_DECOMP_IFD if mode == "ifd" else _lib.QAOA_DECOMP_GIVEN
+        md = {"ifd": _lib.QAOA_DECOMP_IFD, "bfs": _lib.QAOA_DECOMP_BFS,
+              "pfs": _lib.QAOA_DECOMP_PFS, "given": _lib.QAOA_DECOMP_GIVEN}[mode]
         ch = None
         if md == _lib.QAOA_DECOMP_GIVEN:
             ch = _dev(choices, "choices", torch.int32)

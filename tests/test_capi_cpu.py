@@ -223,3 +223,17 @@ def test_cobyla_arguments(hctx):
                dict(ptrs=(0, 1, 1, 1)), dict(ptrs=(1, 0, 1, 1)), dict(ptrs=(1, 1, 0, 1)),
                dict(ptrs=(1, 1, 1, 0))):
         assert call(**kw) == _lib.ERR_INVALID_ARG, kw
+
+
+def test_traversal_arguments(hctx):
+    L = _lib.load()
+
+    def call(N=100, mode=_lib.QAOA_DECOMP_PFS, m=10, k=12, ptrs=(1, 1, 1, 1)):
+        a = [_P(v) for v in ptrs]
+        return L.qaoa_traversal_choices(hctx, N, a[0], a[1], a[2], mode, m, k, a[3], None)
+    assert call() == _lib.ERR_NO_DEVICE
+    assert call(mode=_lib.QAOA_DECOMP_BFS) == _lib.ERR_NO_DEVICE
+    for kw in (dict(mode=_lib.QAOA_DECOMP_IFD), dict(mode=7), dict(N=20000), dict(k=0),
+               dict(k=101), dict(m=0), dict(ptrs=(0, 1, 1, 1)), dict(ptrs=(1, 0, 1, 1)),
+               dict(ptrs=(1, 1, 0, 1)), dict(ptrs=(1, 1, 1, 0))):
+        assert call(**kw) == _lib.ERR_INVALID_ARG, kw

@@ -190,3 +190,66 @@ def test_dqaoa_cycle_replays_through_the_oracle(api, mode):
     assert np.array_equal(xf, xo)
     assert st["accepted"] == int(acc.sum())
     assert abs(e.item() - eo) <= tol(Q)
+
+
+# ---- BFS / PFS windows ------------------------------------------------------
+
+from oracle.traversal import traversal_choices as oracle_traversal  # noqa: E402
+
+
+@pytest.mark.parametrize("mode", ["bfs", "pfs"])
+def test_traversal_golden_shape(api, mode):
+    # the seven-variable example shaped like the paper's traversal figure
+    Q = np.zeros((7, 7))
+    for a, b in ((0, 1), (0, 3), (1, 6), (3, 4)):
+        Q[a, b] = Q[b, a] = 0.5
+    imp = np.array([9, 3, 1, 5, 4, 0.5, 2], dtype=np.float64)
+    order = cycle.rank(imp)
+    for k in (1, 3, 4, 5, 6, 7):
+        ch = api.traversal_choices(cuda(Q), cuda(imp), cuda(order, torch.int32), 7, k, mode)
+        assert np.array_equal(ch.cpu().numpy(), oracle_traversal(Q, imp, order, 7, k, mode)), k
+
+
+@pytest.mark.parametrize("mode", ["bfs", "pfs"])
+@pytest.mark.parametrize("N,m,k,kind", [(200, 100, 12, "maxcut"), (300, 40, 20, "dense"),
+                                        (64, 30, 16, "blocks"), (1000, 500, 12, "maxcut")])
+def test_traversal_against_oracle(api, mode, N, m, k, kind):
+    if kind == "maxcut":
+        Q, _ = workloads.maxcut_qubo(N, N + 1)
+    elif kind == "dense":
+        Q = workloads.qubo(N, N + 2)
+    else:  # disconnected 8-variable blocks: every window has to restart
+        Q = np.zeros((N, N))
+        for b0 in range(0, N, 8):
+            blk = np.random.default_rng(b0).uniform(-1, 1, (8, 8))
+            Q[b0:b0 + 8, b0:b0 + 8] = np.triu(blk) + np.triu(blk, 1).T
+    x = np.random.default_rng(N).integers(0, 2, N).astype(np.uint8)
+    print(f"traversal {mode} N={N} {kind}", flush=True)
+    Qd = cuda(Q)
+    imp, _, order, _ = api.impact(Qd, cuda(x, torch.uint8))
+    ch = api.traversal_choices(Qd, imp, order, m, k, mode).cpu().numpy()
+    ref = oracle_traversal(Q, imp.cpu().numpy(), order.cpu().numpy(), m, k, mode)
+    assert np.array_equal(ch, ref)
+
+
+@pytest.mark.parametrize("mode", ["bfs", "pfs"])
+def test_dqaoa_cycle_traversal_replays(api, mode):
+    from paper_2506_10531_amd import serve
+    N, m, k, p = 90, 10, 8, 1
+    Q, _ = workloads.maxcut_qubo(N, 5)
+    x0 = np.random.default_rng(6).integers(0, 2, N).astype(np.uint8)
+    g0, b0 = workloads.params(1, p, 7)
+    g0, b0 = g0[0], b0[0]
+    Qd, xd = cuda(Q), cuda(x0, torch.uint8)
+    kw = dict(prec="c64", p=p, evals=6, shots=128)
+    with serve.SolveQueue(max_slots=8, **kw) as q:
+        _, e, st = q.dqaoa_cycle(Qd, xd, g0, b0, m, k, mode=mode, seed=300)
+    imp, _, order, _ = api.impact(Qd, cuda(x0, torch.uint8))
+    ch = oracle_traversal(Q, imp.cpu().numpy(), order.cpu().numpy(), m, k, mode)
+    sq = cycle.subqubos(Q, ch)
+    with serve.SolveQueue(max_slots=1, **kw) as q:
+        ts = [q.submit(sq[t], g0, b0, 300 + t) for t in range(m)]
+        best = np.array([q.wait(t, timeout_s=120)["best_z"] for t in ts], dtype=np.uint64)
+    xo, eo, acc = cycle.aggregate(Q, x0, ch, best)
+    assert np.array_equal(xd.cpu().numpy(), xo)
+    assert st["accepted"] == int(acc.sum()) and abs(e.item() - eo) <= tol(Q)
