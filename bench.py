@@ -82,6 +82,8 @@ def parse():
                     help="requests of the same trace replayed against the one-at-a-time "
                          "queue (-1: all of them)")
     ap.add_argument("--serving-slots", type=int, default=256)
+    ap.add_argument("--maxcut-cycles", type=int, default=3,
+                    help="DQAOA cycles per decomposition on the sparse Max-Cut QUBO (0: skip)")
     ap.add_argument("--cobyla-subqubos", type=int, default=64,
                     help="sub-QUBOs of the COBYLA (p=1) versus device-Adam leg (0: skip)")
     ap.add_argument("--dqaoa-cycles", type=int, default=2,
@@ -290,6 +292,47 @@ def dqaoa_leg(cycles: int, no_cpu: bool):
             "cores": cores, "kind": "oracle",
             "sample": "impact factors by N full energy evaluations, IFD windows, sub-QUBOs; "
                       "aggregation of 160 random sub-solutions by full energy evaluations"}
+    return out
+
+
+def maxcut_leg(cycles: int):
+    """DQAOA on a sparse Max-Cut QUBO (Sec. VI-B: N = 1000 nodes, N(N-1)/8
+    random edges, sub-QUBOs of 12 variables, as many sub-QUBOs as half the
+    nodes) with each decomposition: random windows, IFD, BFS and PFS; p = 1,
+    30 Adam evaluations + 256 shots per sub-QUBO, complex64.  Reports the cut
+    after each cycle (the paper's approximation ratio needs reference
+    energies that are not available) and the cycle times."""
+    import numpy as np
+    import torch
+
+    from paper_2506_10531_amd import serve, workloads
+
+    N, k, p = 1000, 12, 1
+    m = N // 2
+    Qh, edges = workloads.maxcut_qubo(N, 41)
+    x0 = np.random.default_rng(42).integers(0, 2, N).astype(np.uint8)
+    g0, b0 = workloads.params(1, p, 43)
+    Q = torch.as_tensor(Qh, device="cuda:0")
+    out = {"workload": f"maxcut_n{N}: {len(edges)} edges, {m} sub-QUBOs of {k} variables, p=1, "
+                       "30 Adam evaluations + 256 shots each, complex64",
+           "initial_cut": int(-(x0.astype(np.float64) @ Qh @ x0))}
+    rng = np.random.default_rng(44)
+    with serve.SolveQueue(prec="c64", p=p, evals=30, shots=256, max_slots=512) as q:
+        for mode in ("random", "ifd", "bfs", "pfs"):
+            x = torch.as_tensor(x0, device="cuda:0")
+            cuts, ms = [], []
+            for c in range(cycles):
+                ch = None
+                if mode == "random":
+                    ch = torch.as_tensor(np.stack([np.sort(rng.choice(N, size=k, replace=False))
+                                                   for _ in range(m)]).astype(np.int32),
+                                         device="cuda:0")
+                _, e, st = q.dqaoa_cycle(Q, x, g0[0], b0[0], m, k,
+                                         mode="given" if mode == "random" else mode,
+                                         choices=ch, seed=7000 * c)
+                cuts.append(int(round(-st["energy"])))
+                ms.append(st["decompose_ms"] + st["solve_ms"] + st["aggregate_ms"])
+            out[mode] = {"cut_per_cycle": cuts, "ms_per_cycle": float(np.mean(ms))}
     return out
 
 
@@ -506,6 +549,8 @@ def main():
         out["dqaoa"] = dqaoa_leg(args.dqaoa_cycles, args.no_cpu_baseline)
     if args.cobyla_subqubos > 0:
         out["cobyla_p1"] = cobyla_leg(args.cobyla_subqubos)
+    if args.maxcut_cycles > 0:
+        out["maxcut"] = maxcut_leg(args.maxcut_cycles)
     print(json.dumps(out))
 
 
