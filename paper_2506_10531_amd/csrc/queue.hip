@@ -123,11 +123,91 @@ struct qaoa_queue {
   char* hRes = nullptr;      // results of one step
   size_t hRes_bytes = 0;
 
+  // Captured evaluation steps: the gather, adjoint pipeline and Adam update
+  // of one n-group, replayed while the group's size and its places in the
+  // arena and index buffer recur (the index contents are uploaded before
+  // each replay).  Bounded; the least recently used graph goes first.
+  struct GraphKey {
+    int n, nb;
+    const char* base;
+    const int* ie;
+    bool operator<(const GraphKey& o) const {
+      if (n != o.n) return n < o.n;
+      if (nb != o.nb) return nb < o.nb;
+      if (base != o.base) return base < o.base;
+      return ie < o.ie;
+    }
+  };
+  struct GraphEntry {
+    hipGraphExec_t exec;
+    uint64_t last;
+  };
+  std::map<GraphKey, GraphEntry> graphs;
+  bool use_graphs = true;
+  uint64_t step_no = 0;
+  long long graph_launches = 0, graph_captures = 0;
+
   size_t request_bytes(int n) const;
   void run();
   int step();
+  int eval_group(const GroupPlan& g, const int* ie, char* base, hipStream_t s);
+  int enqueue_eval(const GroupPlan& g, const int* ie, char* base, hipStream_t s);
   void complete(Request* r, int status);
 };
+
+// One evaluation of an n-group: gather its requests' Q and parameters,
+// the adjoint pipeline, the Adam update.  Kernels only (capturable).
+int qaoa_queue::enqueue_eval(const GroupPlan& g, const int* ie, char* base, hipStream_t s) {
+  const int n = g.n, nb = (int)g.ev.size(), p = o.p;
+  auto A = [&](size_t i) { return base + g.cv.off[i]; };
+  double *Q = (double*)A(g.iQe), *gg = (double*)A(g.iGe), *bb = (double*)A(g.iBe);
+  double *E = (double*)A(g.iE), *dg = (double*)A(g.iDg), *db = (double*)A(g.iDb);
+  hipError_t e = launch_gather(nb, n, p, ie, dQ, QN_MAX * QN_MAX, dG, dB, nullptr, Q, gg, bb,
+                               nullptr, s);
+  if (e != hipSuccess) return hip_error(e, "gather");
+  int rc = enqueue_grad(g.lg, A(g.iGrad), Q, gg, bb, E, dg, db, s, nullptr);
+  if (rc) return rc;
+  e = launch_adam(nb, p, ie, dG, dB, dM, dV, dg, db, dT, o.lr, o.beta1, o.beta2, o.eps, s);
+  if (e != hipSuccess) return hip_error(e, "adam");
+  return QAOA_OK;
+}
+
+// The group's evaluation as a graph replay when its shape recurs, captured
+// on first use; eager when graphs are off.
+int qaoa_queue::eval_group(const GroupPlan& g, const int* ie, char* base, hipStream_t s) {
+  if (!use_graphs) return enqueue_eval(g, ie, base, s);
+  const GraphKey key{g.n, (int)g.ev.size(), base, ie};
+  auto it = graphs.find(key);
+  if (it == graphs.end()) {
+    if (graphs.size() >= 256) {  // evict the least recently used (not in flight:
+      auto lru = graphs.begin();  // every step ends with its streams drained)
+      for (auto j = graphs.begin(); j != graphs.end(); ++j)
+        if (j->second.last < lru->second.last) lru = j;
+      (void)hipGraphExecDestroy(lru->second.exec);
+      graphs.erase(lru);
+    }
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");
+    int rc = enqueue_eval(g, ie, base, s);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (rc || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc ? rc : hip_error(e2, "hipStreamEndCapture");
+    }
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_error(e, "hipGraphInstantiate");
+    it = graphs.emplace(key, GraphEntry{ex, step_no}).first;
+    ++graph_captures;
+  }
+  it->second.last = step_no;
+  hipError_t e = hipGraphLaunch(it->second.exec, s);
+  if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
+  ++graph_launches;
+  return QAOA_OK;
+}
 
 size_t qaoa_queue::request_bytes(int n) const {
   Layout lg, ls;
@@ -158,6 +238,7 @@ void qaoa_queue::complete(Request* r, int status) {
 // One scheduler step over all admitted requests.  Called without the lock
 // held; takes it for bookkeeping only.
 int qaoa_queue::step() {
+  ++step_no;
   std::vector<Request*> act, fresh;
   {
     std::lock_guard<std::mutex> lk(mu);
@@ -280,15 +361,8 @@ int qaoa_queue::step() {
     const int* is = dIdx + idx_off[gi].second;
     auto A = [&](size_t i) { return base + g.cv.off[i]; };
     if (nb) {
-      double *Q = (double*)A(g.iQe), *gg = (double*)A(g.iGe), *bb = (double*)A(g.iBe);
-      double *E = (double*)A(g.iE), *dg = (double*)A(g.iDg), *db = (double*)A(g.iDb);
-      e = launch_gather(nb, n, p, ie, dQ, QN_MAX * QN_MAX, dG, dB, nullptr, Q, gg, bb,
-                        nullptr, s);
-      if (e != hipSuccess) return hip_error(e, "gather");
-      int rc = enqueue_grad(g.lg, A(g.iGrad), Q, gg, bb, E, dg, db, s, nullptr);
+      int rc = eval_group(g, ie, base, s);
       if (rc) return rc;
-      e = launch_adam(nb, p, ie, dG, dB, dM, dV, dg, db, dT, o.lr, o.beta1, o.beta2, o.eps, s);
-      if (e != hipSuccess) return hip_error(e, "adam");
     }
     if (ns) {
       double *Q = (double*)A(g.iQs), *gg = (double*)A(g.iGs), *bb = (double*)A(g.iBs);
@@ -426,6 +500,10 @@ int qaoa_queue_create(qaoa_ctx* ctx, const qaoa_queue_opts* opts, qaoa_queue** o
   if (!o.batched) q->o.max_slots = 1;
   q->device = dev;
   q->budget = o.hbm_budget ? o.hbm_budget : ctx_budget(ctx) / 2;
+  {  // DQAOA_QUEUE_GRAPHS=0 runs every evaluation step eagerly
+    const char* v = getenv("DQAOA_QUEUE_GRAPHS");
+    q->use_graphs = !(v && strcmp(v, "0") == 0);
+  }
   const int S = q->o.max_slots, p = o.p;
   if (hipSetDevice(dev) != hipSuccess) return set_error(QAOA_ERR_HIP, "hipSetDevice");
   hipError_t e = hipSuccess;
@@ -471,10 +549,11 @@ int qaoa_queue_destroy(qaoa_queue* q) {
   if (q->th.joinable()) q->th.join();
   (void)hipSetDevice(q->device);
   for (int i = 0; i < NSTREAMS; ++i)
-    if (q->streams[i]) {
-      (void)hipStreamSynchronize(q->streams[i]);
-      (void)hipStreamDestroy(q->streams[i]);
-    }
+    if (q->streams[i]) (void)hipStreamSynchronize(q->streams[i]);
+  for (auto& kv : q->graphs) (void)hipGraphExecDestroy(kv.second.exec);
+  q->graphs.clear();
+  for (int i = 0; i < NSTREAMS; ++i)
+    if (q->streams[i]) (void)hipStreamDestroy(q->streams[i]);
   if (q->ev_up) (void)hipEventDestroy(q->ev_up);
   void* dev[] = {q->arena, q->dQ, q->dG, q->dB, q->dM, q->dV, q->dT, q->dSeed, q->dIdx};
   for (void* ptr : dev)

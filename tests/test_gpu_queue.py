@@ -129,3 +129,21 @@ def test_admission_respects_budget(serve):
     # FIFO: admission times are ordered by submission
     adm = [r["t_admit_ns"] for r in rs]
     assert adm == sorted(adm)
+
+
+def test_graph_replays_equal_eager_steps(serve, monkeypatch):
+    """Evaluation steps replayed from captured graphs give bitwise the
+    results of eager steps (every request runs many replays, with the index
+    uploads and other groups' eager work in between)."""
+    p, evals, shots = 2, 12, 64
+    mix = reqs(12, p, 40, n_lo=4, n_hi=17)
+    kw = dict(prec="c64", p=p, evals=evals, shots=shots, max_slots=6)
+    monkeypatch.setenv("DQAOA_QUEUE_GRAPHS", "1")
+    with_graphs = _run(serve, mix, **kw)
+    monkeypatch.setenv("DQAOA_QUEUE_GRAPHS", "0")
+    eager = _run(serve, mix, **kw)
+    for a, b in zip(with_graphs, eager):
+        assert a["status"] == 0 and b["status"] == 0
+        assert np.array_equal(a["gamma"], b["gamma"]) and np.array_equal(a["beta"], b["beta"])
+        assert a["expect"] == b["expect"]
+        assert np.array_equal(a["samples"], b["samples"])
