@@ -227,15 +227,16 @@ bool make_plan_reg14(int n, int p, Plan* P) {
   return n >= 15 && make_plan_regtile(n, p, 14, 4, P);
 }
 
-bool make_plan_reg13(int n, int p, Plan* P) {
+bool make_plan_reg2set(int n, int p, int K, int C, Plan* P) {
   *P = Plan();
-  if (n < 14 || n > 22 || p < 1 || p > 64) return false;
-  const int a = n - 9 < 4 ? 4 : n - 9;
-  P->K = 13;
+  const int span = K - C;
+  if (n <= K || n > K + span || p < 1 || p > 64) return false;
+  const int a = n - span < C ? C : n - span;
+  P->K = K;
   P->sets = 2;
-  P->c = 4;
-  P->k[0] = P->k[1] = 13;
-  P->a[0] = 13;
+  P->c = C;
+  P->k[0] = P->k[1] = K;
+  P->a[0] = K;
   P->a[1] = a;
   auto desc = [&](int set, int lead, int ja, int jb) {
     PassDesc d{};
@@ -244,16 +245,16 @@ bool make_plan_reg13(int n, int p, Plan* P) {
     d.lead = lead;
     d.ja = ja;
     d.jb = jb;
-    d.k = 13;
+    d.k = K;
     if (set == 0) {
-      d.c = 13;
-      d.a = 13;
+      d.c = K;
+      d.a = K;
       d.mixlo = 0;
       d.kind = 1;
     } else {
-      d.c = 4;
+      d.c = C;
       d.a = a;
-      d.mixlo = 4 + (13 - a);
+      d.mixlo = C + (K - a);
       d.kind = 2;
     }
     return d;
@@ -271,12 +272,26 @@ bool make_plan_reg13(int n, int p, Plan* P) {
   return true;
 }
 
-static bool use_reg13(int op, int prec, int n) {
+bool make_plan_reg13(int n, int p, Plan* P) {
+  return n >= 14 && n <= 22 && make_plan_reg2set(n, p, 13, 4, P);
+}
+
+static bool grad_reg_off() {
   static const bool off = [] {
     const char* v = getenv("DQAOA_GRAD_KERNEL");
     return v && strcmp(v, "lds") == 0;
   }();
-  return !off && op == OP_GRAD && prec == QAOA_C64 && n >= 14 && n <= 22;
+  return off;
+}
+
+// Register-tile gradients: complex64 on 13-qubit tiles (14 <= n <= 22),
+// complex128 on 12-qubit tiles (13 <= n <= 22); DQAOA_GRAD_KERNEL=lds
+// selects the LDS-tile adjoint instead.
+static bool use_reg13(int op, int prec, int n) {
+  return !grad_reg_off() && op == OP_GRAD && prec == QAOA_C64 && n >= 14 && n <= 22;
+}
+static bool use_reg12(int op, int prec, int n) {
+  return !grad_reg_off() && op == OP_GRAD && prec == QAOA_C128 && n >= 13 && n <= 22;
 }
 
 // The register-tile kernels serve forward evaluations with n >= 15
@@ -302,6 +317,7 @@ bool choose_plan(int op, int prec, int n, int p, Plan* P) {
   if (use_reg14(op, prec, n)) return make_plan_reg14(n, p, P);
   if (use_reg13d(op, prec, n)) return make_plan_regtile(n, p, 13, 2, P);
   if (use_reg13(op, prec, n)) return make_plan_reg13(n, p, P);
+  if (use_reg12(op, prec, n)) return make_plan_reg2set(n, p, 12, 2, P);
   return make_plan(n, p, kmax_for(prec, op == OP_GRAD), cpref_for(prec), P);
 }
 
@@ -467,20 +483,25 @@ int enqueue_grad(const Layout& L, char* base, const double* Q,
   const double sb = (double)L.state_bytes * L.nstates;
   auto ck = [&](int i) { return (void*)L.at(base, L.iCk[i]); };
   void* lam = np > 1 ? (void*)L.at(base, L.iLam) : nullptr;
-  if (P.K == 13 && P.pass[0].kind != 0) {
+  if ((P.K == 13 || P.K == 12) && P.pass[0].kind != 0) {
+    const bool c128 = P.K == 12;
     // register-tile gradient: checkpoint passes, the seed pass, middle
     // adjoint passes, and the first pass's adjoint
     for (int i = 0; i + 1 < np; ++i) {
       PassDesc d = P.pass[i];
       TimerScope ts(tm, s, (i == 0 ? 0.0 : sb) + sb);
-      e = launch_fwd13_ckpt_pass(d, ns, S, p, i ? ck(i - 1) : nullptr, ck(i), stride, W, coef, s);
+      e = c128 ? launch_fwd12_ckpt_pass(d, ns, S, p, i ? ck(i - 1) : nullptr, ck(i), stride, W,
+                                        coef, s)
+               : launch_fwd13_ckpt_pass(d, ns, S, p, i ? ck(i - 1) : nullptr, ck(i), stride, W,
+                                        coef, s);
       if (e != hipSuccess) return hip_error(e, "checkpoint pass");
     }
     for (int i = np - 1; i >= 0; --i) {
       const int shape = i == np - 1 ? 0 : (i == 0 ? 2 : 1);
       TimerScope ts(tm, s, (shape == 1 ? 3 : 2) * sb);
-      e = launch_bwd13_pass(P.pass[i], shape, ns, S, p, ck(i == np - 1 ? i - 1 : i), lam, stride,
-                            W, coef, part, L.rec_base[i], L.nrec, s);
+      e = (c128 ? launch_bwd12_pass : launch_bwd13_pass)(
+          P.pass[i], shape, ns, S, p, ck(i == np - 1 ? i - 1 : i), lam, stride, W, coef, part,
+          L.rec_base[i], L.nrec, s);
       if (e != hipSuccess) return hip_error(e, "adjoint pass");
     }
     double* outs[3] = {dgamma, dbeta, expect};

@@ -79,6 +79,9 @@ bool make_plan_reg14(int n, int p, Plan* out);
 // <= 22): set 0 = [0, 13), set 1 = [13, n) on tile bits [0, 4) + [a, a + 9).
 // No pending scalars: the checkpoint passes store true-scaled states.
 bool make_plan_reg13(int n, int p, Plan* out);
+// The same two-set plan for any tile size K and C low bits (K = 12, C = 2:
+// the complex128 gradient, 13 <= n <= 22).
+bool make_plan_reg2set(int n, int p, int K, int C, Plan* out);
 
 hipError_t launch_fwd14_pass(const PassDesc& d, int nstates, int S, int p,
                              const void* in, void* out, uint64_t state_stride,
@@ -97,6 +100,15 @@ hipError_t launch_fwd13_ckpt_pass(const PassDesc& d, int nstates, int S, int p, 
                                   void* out, uint64_t stride, const double* W,
                                   const LayerCoef* coef, hipStream_t stream);
 hipError_t launch_bwd13_pass(const PassDesc& d, int shape, int nstates, int S, int p,
+                             const void* psi, void* lam, uint64_t stride, const double* W,
+                             const LayerCoef* coef, double* part, int rec_base, int nrec,
+                             hipStream_t stream);
+// Gradient passes on 12-qubit register tiles (complex128), as the 13-qubit
+// complex64 ones: 13 <= n <= 22, kind-2 sets with 2 low bits.
+hipError_t launch_fwd12_ckpt_pass(const PassDesc& d, int nstates, int S, int p, const void* in,
+                                  void* out, uint64_t stride, const double* W,
+                                  const LayerCoef* coef, hipStream_t stream);
+hipError_t launch_bwd12_pass(const PassDesc& d, int shape, int nstates, int S, int p,
                              const void* psi, void* lam, uint64_t stride, const double* W,
                              const LayerCoef* coef, double* part, int rec_base, int nrec,
                              hipStream_t stream);

@@ -198,12 +198,16 @@ __device__ __forceinline__ void mix_round(typename G::V (&v)[Dim<G>::NA], typena
 // (every 32-bit word of the register pair is swapped).
 template <class G, int SR, int SL>
 __device__ __forceinline__ void swap_slot(typename G::V (&v)[Dim<G>::NA]) {
-  static_assert(SL == 4 || SL == 5, "lane slots 4 and 5 only");
+  static_assert(SL == 3 || SL == 4 || SL == 5, "lane slots 3, 4 and 5 only");
   using V = typename G::V;
   constexpr int NA = Dim<G>::NA, NW = sizeof(V) / 4;
   struct Words {
     unsigned w[NW];
   };
+  // lane slot 3 (lane bit 3): no swap instruction; each lane sends the word
+  // its xor-8 partner needs (DPP row rotation by 8 within a 16-lane row is
+  // that exchange) and keeps the other
+  const bool c3 = SL == 3 && ((threadIdx.x >> 3) & 1);
 #pragma unroll
   for (int r = 0; r < NA; ++r) {
     if ((r >> SR) & 1) continue;
@@ -211,7 +215,12 @@ __device__ __forceinline__ void swap_slot(typename G::V (&v)[Dim<G>::NA]) {
     Words w1 = __builtin_bit_cast(Words, v[r | (1 << SR)]);
 #pragma unroll
     for (int k = 0; k < NW; ++k) {
-      if (SL == 5) {
+      if (SL == 3) {
+        const unsigned send = c3 ? w0.w[k] : w1.w[k];
+        const unsigned recv = (unsigned)__builtin_amdgcn_mov_dpp((int)send, 0x128, 0xF, 0xF, false);
+        if (c3) w0.w[k] = recv;
+        else w1.w[k] = recv;
+      } else if (SL == 5) {
         const auto px = __builtin_amdgcn_permlane32_swap(w0.w[k], w1.w[k], false, false);
         w0.w[k] = px[0];
         w1.w[k] = px[1];

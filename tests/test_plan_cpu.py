@@ -51,6 +51,7 @@ def test_plan_geometry_and_semantics(hctx, prec, n, p, grad):
     reg14 = prec == 1 and not grad and n >= 15
     reg13 = prec == 1 and grad and 14 <= n <= 22
     reg13d = prec == 0 and not grad and n >= 14
+    reg12 = prec == 0 and grad and 13 <= n <= 22
     ps = passes(hctx, prec, n, p, grad)
     if reg13d:
         # 13-qubit complex128 tiles, 2 contiguous low bits in the other sets:
@@ -58,11 +59,11 @@ def test_plan_geometry_and_semantics(hctx, prec, n, p, grad):
         assert len(ps) == (p + 1 if n <= 24 else 2 * p + 1)
     for i, d in enumerate(ps):
         assert 1 <= d["k"] <= min(kmax, n)
-        assert (d["kind"] != 0) == (reg14 or reg13 or reg13d)
-        if reg14 or reg13 or reg13d:
-            assert d["k"] == (14 if reg14 else 13)
+        assert (d["kind"] != 0) == (reg14 or reg13 or reg13d or reg12)
+        if reg14 or reg13 or reg13d or reg12:
+            assert d["k"] == (14 if reg14 else 12 if reg12 else 13)
             assert d["kind"] == (1 if d["set"] == 0 else 2)
-            assert d["c"] == (d["k"] if d["set"] == 0 else (2 if reg13d else 4))
+            assert d["c"] == (d["k"] if d["set"] == 0 else (2 if (reg13d or reg12) else 4))
         tb = tile_bits(d, n)
         assert len(tb) == d["k"] and len(set(tb)) == d["k"]
         assert all(0 <= b < n for b in tb)
