@@ -247,9 +247,13 @@ bwd_kernel(BwdArgs A) {
   const V sc = mkv<V>(sr, si);
   const bool sw = KIND == 1 && BT == B_MID && (L1.mode != 0) != (L2.mode != 0);
   // factors that undo the phase of layer jb (B_MID), computed before the
-  // undo so that they do not interleave with it
+  // undo so that they do not interleave with it (complex64); the FP64 factors
+  // of complex128 tiles are formed where they are used, so that they do not
+  // hold 20 VGPRs through the first undo
+  constexpr bool EARLY_P = sizeof(V) == 8;
   PhaseF<G::R, V> P;
-  if (BT == B_MID) P = phase_factors<G, PL>(&T, fl, cblk, lane, wave, gp_undo, 1.0, 0.0);
+  if (BT == B_MID && EARLY_P)
+    P = phase_factors<G, PL>(&T, fl, cblk, lane, wave, gp_undo, 1.0, 0.0);
   double se = 0.0, sn = 0.0, sg = 0.0, sb1 = 0.0, sb2 = 0.0;
   if (BT == B_SEED) {
     // forward lead half-mixer on psi, then <C>, norm and lambda = C psi
@@ -289,6 +293,7 @@ bwd_kernel(BwdArgs A) {
     sg = block_sum(ag, tmp) * wa2;
     if (BT == B_MID) {
       // undo the phase of layer jb, then the lead (layer jb - 1)
+      if (!EARLY_P) P = phase_factors<G, PL>(&T, fl, cblk, lane, wave, gp_undo, 1.0, 0.0);
       phase_tree<G::R, G::R - 1>(P, KF, P.f0, 0, [&](int r, V f) {
         vp[r] = cmul(vp[r], f);
         vl[r] = cmul(vl[r], f);
