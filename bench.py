@@ -90,6 +90,11 @@ def parse():
                     help="DQAOA outer cycles on the N=1000 QUBO (0: skip)")
     ap.add_argument("--large-steps", type=int, default=3,
                     help="steps of the n=32 large-state workload (0: skip)")
+    ap.add_argument("--grad-steps", type=int, default=5,
+                    help="gradient calls per precision on the 512 x n=16, p=6 "
+                         "differentiation workload (0: skip)")
+    ap.add_argument("--legs", default="serving,large,dqaoa,cobyla,maxcut,grad",
+                    help="comma-separated legs to run after the main workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a 2 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -236,6 +241,53 @@ def large_state_leg(steps: int):
         "frac": achieved / PEAK_HBM_GBPS,
         "expect": [float(x) for x in en],
     }
+
+
+def grad_leg(steps: int):
+    """The differentiation workload (512 dense n = 16 QUBOs, p = 6): qaoa_grad
+    in each precision, timed over `steps` calls, with the adjoint and
+    checkpoint passes' bandwidth from the library's per-launch events."""
+    import torch
+
+    from paper_2506_10531_amd import api, workloads
+
+    W = workloads.WORKLOADS["diff_n16"]
+    B, n, p = W["batch"], W["n"], W["p"]
+    dev = torch.device("cuda:0")
+    Q = torch.as_tensor(workloads.qubos(B, n, W["q_seed"]), device=dev)
+    g, b = workloads.params(B, p, W["p_seed"])
+    gd = torch.as_tensor(g, device=dev).reshape(B, 1, p)
+    bd = torch.as_tensor(b, device=dev).reshape(B, 1, p)
+    ctx = api.Context(0)
+    res = {"workload": f"diff_n16: {B} dense n={n} QUBOs, p={p}, one parameter set each",
+           "steps": steps}
+    for prec in ("c64", "c128"):
+        plan = ctx.plan(prec, B, n, p, 1, grad=True)
+        for _ in range(2):
+            api.grad(Q, gd, bd, prec=prec, ctx=ctx)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_read(reset=True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            api.grad(Q, gd, bd, prec=prec, ctx=ctx)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ctx.profile(False)
+        launches, pass_ms, pass_bytes = ctx.profile_read(reset=True)
+        achieved = pass_bytes / (pass_ms * 1e-3) / 1e9
+        res[prec] = {
+            "ms_per_grad": 1e3 * wall / steps,
+            "grads_per_s": B * steps / wall,
+            "launches_per_grad": launches / steps,
+            "pass_ms_per_grad": pass_ms / steps,
+            "bytes_per_grad": pass_bytes / steps,
+            "achieved_GBps": achieved,
+            "frac": achieved / PEAK_HBM_GBPS,
+            "tile_qubits": plan["tile_qubits"],
+        }
+    ctx.close()
+    return res
 
 
 def dqaoa_leg(cycles: int, no_cpu: bool):
@@ -541,18 +593,21 @@ def main():
             ec = e_other if prec == "c64" else e_main
             out["errors"]["c128_vs_oracle_expect_max_rel"] = float(
                 np.max(np.abs(ec[:k] - eo) / np.maximum(np.abs(eo), 1.0)))
-    if args.serving_requests > 0:
+    legs = set(x for x in args.legs.split(",") if x)
+    if args.serving_requests > 0 and "serving" in legs:
         out["serving"] = serving_leg(args.serving_requests, args.serving_single,
                                      args.serving_slots,
                                      calib=min(256, args.serving_requests))
-    if args.large_steps > 0:
+    if args.large_steps > 0 and "large" in legs:
         out["large_state"] = large_state_leg(args.large_steps)
-    if args.dqaoa_cycles > 0:
+    if args.dqaoa_cycles > 0 and "dqaoa" in legs:
         out["dqaoa"] = dqaoa_leg(args.dqaoa_cycles, args.no_cpu_baseline)
-    if args.cobyla_subqubos > 0:
+    if args.cobyla_subqubos > 0 and "cobyla" in legs:
         out["cobyla_p1"] = cobyla_leg(args.cobyla_subqubos)
-    if args.maxcut_cycles > 0:
+    if args.maxcut_cycles > 0 and "maxcut" in legs:
         out["maxcut"] = maxcut_leg(args.maxcut_cycles)
+    if args.grad_steps > 0 and "grad" in legs:
+        out["grad"] = grad_leg(args.grad_steps)
     print(json.dumps(out))
 
 
