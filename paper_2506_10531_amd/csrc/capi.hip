@@ -142,15 +142,15 @@ bool make_plan(int n, int p, int kmax, int cpref, Plan* P) {
 // into runs of at most K - C, and set i's tile is the C low bits plus the
 // (K - C)-bit run [a, a + K - C) that ends at its mixed run (or at n), so it
 // carries (does not mix) any of those bits below its own run.
-bool make_plan_regtile(int n, int p, int K, int C, Plan* P) {
+bool make_plan_regtile(int n, int p, int K, int C, Plan* P, int cmax) {
   *P = Plan();
   P->K = K;
   const int span = K - C;
-  if (n <= K || n > 34 || p < 1 || p > 64 || span < 1) return false;
+  if (n <= K || n > 34 || p < 1 || p > 64 || span < 1 || cmax < C || cmax >= K) return false;
   const int m = 1 + (n - K + span - 1) / span;
   if (m > 4) return false;
   const int rest = n - K, q = m - 1;
-  int lo[4] = {0}, hi[4] = {0}, a[4] = {0};
+  int lo[4] = {0}, hi[4] = {0}, a[4] = {0}, cs[4] = {K, C, C, C};
   lo[0] = 0;
   hi[0] = K;
   int cur = K;
@@ -159,8 +159,12 @@ bool make_plan_regtile(int n, int p, int K, int C, Plan* P) {
     lo[i] = cur;
     hi[i] = cur + run;
     cur += run;
-    a[i] = hi[i] - span < C ? C : hi[i] - span;
-    if (a[i] + span > n) a[i] = n - span;
+    // as many contiguous low bits as the set's run leaves room for (up to
+    // cmax): longer HBM runs, and fewer high bits (pages) per tile
+    cs[i] = K - run < cmax ? K - run : cmax;
+    const int sp = K - cs[i];
+    a[i] = hi[i] - sp < cs[i] ? cs[i] : hi[i] - sp;
+    if (a[i] + sp > n) a[i] = n - sp;
   }
   P->sets = m;
   P->c = C;
@@ -182,9 +186,9 @@ bool make_plan_regtile(int n, int p, int K, int C, Plan* P) {
       d.mixlo = 0;
       d.kind = 1;
     } else {
-      d.c = C;
+      d.c = cs[set];
       d.a = a[set];
-      d.mixlo = C + (lo[set] - a[set]);
+      d.mixlo = cs[set] + (lo[set] - a[set]);
       d.kind = 2;
     }
     return d;
@@ -224,7 +228,7 @@ bool make_plan_regtile(int n, int p, int K, int C, Plan* P) {
 }
 
 bool make_plan_reg14(int n, int p, Plan* P) {
-  return n >= 15 && make_plan_regtile(n, p, 14, 4, P);
+  return n >= 15 && make_plan_regtile(n, p, 14, 4, P, 8);
 }
 
 bool make_plan_reg2set(int n, int p, int K, int C, Plan* P) {

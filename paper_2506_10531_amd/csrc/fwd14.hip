@@ -43,11 +43,14 @@ using namespace rt;
 //         registers); phase layout of set 0
 //   L_B2  other sets: bits 4, 5, 6, 12, 13 in registers; phase layout
 // Set 0 mixes in A, A1 | transpose | B, B1 and back in reverse; the other
-// sets in A | transpose | B2 and back.
-struct G14 {
+// sets in A | transpose | B2 and back.  C_ is the number of contiguous low
+// tile bits of the other sets (4 to 8): they mix tile bits [MIXLO, 14) with
+// MIXLO >= C_, so bits 1..3, never held in registers, are never mixed by them.
+template <int C_>
+struct G14T {
   using V = float2;
   using S = float;
-  static constexpr int C = 4;
+  static constexpr int C = C_;
   static constexpr int R = 6;
   enum { L_A = 0, L_A1 = 1, L_B = 2, L_B1 = 3, L_B2 = 4 };
   static constexpr int LA = L_A;
@@ -80,44 +83,44 @@ struct G14 {
   static __device__ __forceinline__ void lead(V (&v)[64], V* buf, int lane, int wave, S t,
                                               bool flip) {
     if constexpr (KIND == 1) {
-      constexpr uint32_t D1 = reg_bits_of<G14, L_A>();
-      constexpr uint32_t D2 = D1 | reg_bits_of<G14, L_A1>();
-      constexpr uint32_t D3 = D2 | reg_bits_of<G14, L_B>();
-      mix_round<G14, reg_mask<G14, L_A, 0, MIXLO>()>(v, t);
-      swap_slot<G14, 4, 4>(v);
-      swap_slot<G14, 5, 5>(v);
-      mix_round<G14, reg_mask<G14, L_A1, D1, MIXLO>()>(v, t);
-      transpose<G14, L_A1, L_B, MIXLO>(v, buf, lane, wave, flip);
-      mix_round<G14, reg_mask<G14, L_B, D2, MIXLO>()>(v, t);
-      swap_slot<G14, 5, 4>(v);
-      mix_round<G14, reg_mask<G14, L_B1, D3, MIXLO>()>(v, t);
+      constexpr uint32_t D1 = reg_bits_of<G14T, L_A>();
+      constexpr uint32_t D2 = D1 | reg_bits_of<G14T, L_A1>();
+      constexpr uint32_t D3 = D2 | reg_bits_of<G14T, L_B>();
+      mix_round<G14T, reg_mask<G14T, L_A, 0, MIXLO>()>(v, t);
+      swap_slot<G14T, 4, 4>(v);
+      swap_slot<G14T, 5, 5>(v);
+      mix_round<G14T, reg_mask<G14T, L_A1, D1, MIXLO>()>(v, t);
+      transpose<G14T, L_A1, L_B, MIXLO>(v, buf, lane, wave, flip);
+      mix_round<G14T, reg_mask<G14T, L_B, D2, MIXLO>()>(v, t);
+      swap_slot<G14T, 5, 4>(v);
+      mix_round<G14T, reg_mask<G14T, L_B1, D3, MIXLO>()>(v, t);
     } else {
-      constexpr uint32_t D1 = reg_bits_of<G14, L_A>();
-      mix_round<G14, reg_mask<G14, L_A, 0, MIXLO>()>(v, t);
-      transpose<G14, L_A, L_B2, MIXLO>(v, buf, lane, wave, flip);
-      mix_round<G14, reg_mask<G14, L_B2, D1, MIXLO>()>(v, t);
+      constexpr uint32_t D1 = reg_bits_of<G14T, L_A>();
+      mix_round<G14T, reg_mask<G14T, L_A, 0, MIXLO>()>(v, t);
+      transpose<G14T, L_A, L_B2, MIXLO>(v, buf, lane, wave, flip);
+      mix_round<G14T, reg_mask<G14T, L_B2, D1, MIXLO>()>(v, t);
     }
   }
   template <int KIND, int MIXLO>
   static __device__ __forceinline__ void trail(V (&v)[64], V* buf, int lane, int wave, S t,
                                                bool flip) {
     if constexpr (KIND == 1) {
-      constexpr uint32_t D1 = reg_bits_of<G14, L_B1>();
-      constexpr uint32_t D2 = D1 | reg_bits_of<G14, L_B>();
-      constexpr uint32_t D3 = D2 | reg_bits_of<G14, L_A1>();
-      mix_round<G14, reg_mask<G14, L_B1, 0, MIXLO>()>(v, t);
-      swap_slot<G14, 5, 4>(v);
-      mix_round<G14, reg_mask<G14, L_B, D1, MIXLO>()>(v, t);
-      transpose<G14, L_B, L_A1, MIXLO>(v, buf, lane, wave, flip);
-      mix_round<G14, reg_mask<G14, L_A1, D2, MIXLO>()>(v, t);
-      swap_slot<G14, 4, 4>(v);
-      swap_slot<G14, 5, 5>(v);
-      mix_round<G14, reg_mask<G14, L_A, D3, MIXLO>()>(v, t);
+      constexpr uint32_t D1 = reg_bits_of<G14T, L_B1>();
+      constexpr uint32_t D2 = D1 | reg_bits_of<G14T, L_B>();
+      constexpr uint32_t D3 = D2 | reg_bits_of<G14T, L_A1>();
+      mix_round<G14T, reg_mask<G14T, L_B1, 0, MIXLO>()>(v, t);
+      swap_slot<G14T, 5, 4>(v);
+      mix_round<G14T, reg_mask<G14T, L_B, D1, MIXLO>()>(v, t);
+      transpose<G14T, L_B, L_A1, MIXLO>(v, buf, lane, wave, flip);
+      mix_round<G14T, reg_mask<G14T, L_A1, D2, MIXLO>()>(v, t);
+      swap_slot<G14T, 4, 4>(v);
+      swap_slot<G14T, 5, 5>(v);
+      mix_round<G14T, reg_mask<G14T, L_A, D3, MIXLO>()>(v, t);
     } else {
-      constexpr uint32_t D1 = reg_bits_of<G14, L_B2>();
-      mix_round<G14, reg_mask<G14, L_B2, 0, MIXLO>()>(v, t);
-      transpose<G14, L_B2, L_A, MIXLO>(v, buf, lane, wave, flip);
-      mix_round<G14, reg_mask<G14, L_A, D1, MIXLO>()>(v, t);
+      constexpr uint32_t D1 = reg_bits_of<G14T, L_B2>();
+      mix_round<G14T, reg_mask<G14T, L_B2, 0, MIXLO>()>(v, t);
+      transpose<G14T, L_B2, L_A, MIXLO>(v, buf, lane, wave, flip);
+      mix_round<G14T, reg_mask<G14T, L_A, D1, MIXLO>()>(v, t);
     }
   }
 };
@@ -133,6 +136,7 @@ hipError_t launch_fwd14_pass(const PassDesc& d, int nstates, int S, int p,
   const int pt = pass_shape(d, p);
   if (pt < 0 || (d.kind == 1 && pt == P_LEAD)) return hipErrorInvalidValue;
   if (d.kind == 1 ? d.mixlo != 0 : (d.mixlo < 4 || d.mixlo > 13)) return hipErrorInvalidValue;
+  if (d.kind == 2 && d.c != (d.mixlo < 8 ? d.mixlo : 8)) return hipErrorInvalidValue;
   FwdArgs A;
   A.d = d;
   A.S = S;
@@ -147,7 +151,9 @@ hipError_t launch_fwd14_pass(const PassDesc& d, int nstates, int S, int p,
   const uint64_t total = (uint64_t)nstates << (d.n - 14);
   if (total > 0xFFFFFFFFull) return hipErrorInvalidValue;
   const dim3 grid((unsigned)total), blk(NT);
-#define DQ_K(K, M, T) hipLaunchKernelGGL((fwd_kernel<G14, K, M, T>), grid, blk, 0, stream, A)
+#define DQ_K(K, M, T)                                                                        \
+  hipLaunchKernelGGL((fwd_kernel<G14T<(K == 1 ? 4 : M < 8 ? M : 8)>, K, M, T>), grid, blk, 0, \
+                     stream, A)
 #define DQ_PT(K, M)                         \
   switch (pt) {                             \
     case P_MID: DQ_K(K, M, P_MID); break;   \

@@ -102,6 +102,31 @@ def test_n32_diagonal_q_product_formula(api):
     assert abs(e[0] - ref) <= 1e-5 * np.abs(d).sum(), (e[0], ref)
 
 
+@pytest.mark.parametrize("n", [27, 28, 30])
+def test_three_sets_p1_closed_form(api, n):
+    """Three-set complex64 plans whose kind-2 sets keep 6 to 8 contiguous low
+    qubits (512-byte to 2 KiB runs): first, lead-only and last passes."""
+    Q = workloads.qubo(n, 60 + n)
+    g, b = workloads.params(2, 1, 70 + n)
+    print(f"n={n} p=1 closed form", flush=True)
+    e = api.expect(cuda(Q), cuda(g), cuda(b), prec="c64").cpu().numpy()[0]
+    for s in range(2):
+        cf = dense_ref.p1_closed_form(Q, g[s, 0], b[s, 0])
+        assert abs(e[s] - cf) <= 1e-5 * _cmax_bound(Q), (s, e[s], cf)
+
+
+@pytest.mark.parametrize("n", [28, 30])
+def test_three_sets_diagonal_q_p3(api, n):
+    """The same plans at p = 3 (middle passes on the kind-2 sets)."""
+    rng = np.random.default_rng(n)
+    d = rng.uniform(-1, 1, n)
+    g, b = workloads.params(1, 3, 80 + n)
+    print(f"n={n} diagonal p=3", flush=True)
+    e = api.expect(cuda(np.diag(d)), cuda(g), cuda(b), prec="c64").cpu().numpy()[0]
+    ref = dense_ref.diagonal_expect(d, g[0], b[0])
+    assert abs(e[0] - ref) <= 1e-5 * np.abs(d).sum(), (e[0], ref)
+
+
 def test_large_n32_four_sets_runs_and_is_normalised(api):
     """The n = 32, p = 2, 4-set workload: every set keeps unit norm and the
     four <C> lie within [min C, max C] bounds."""

@@ -70,7 +70,7 @@ def test_single_tile_state_and_expect(api, n, p, prec):
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 @pytest.mark.parametrize("n,p", [(13, 2), (14, 3), (15, 1), (16, 2), (17, 4), (19, 3),
-                                 (21, 2)])
+                                 (21, 2), (22, 2), (23, 1)])
 def test_multipass_state_and_expect(api, n, p, prec):
     run_case(api, n, p, S=2, prec=prec, B=2 if n < 20 else 1)
 
