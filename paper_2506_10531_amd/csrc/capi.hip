@@ -358,6 +358,7 @@ int make_layout(int op, int prec, int B, int n, int p, int S, int shots,
   const Plan& P = L->plan;
   L->iW = L->cv.add((size_t)B * n * n * sizeof(double));
   L->iC = L->cv.add(L->nstates * p * sizeof(LayerCoef));
+  L->iTab = L->cv.add(L->nstates * TAB_BYTES);
   if (!grad) {
     const PassDesc& last = P.pass[P.npass - 1];
     L->iPart = L->cv.add(L->nstates * ntiles(last) * 2 * sizeof(double));
@@ -421,7 +422,8 @@ int run_forward(const Layout& L, char* base, const double* Q,
     TimerScope ts(tm, s, bytes);
     if (d.kind && L.prec == QAOA_C64)
       e = launch_fwd14_pass(d, (int)L.nstates, L.S, L.p, state,
-                            (last && psi) ? psi : state, stride, W, coef, part, probs, s);
+                            (last && psi) ? psi : state, stride, W, coef, part, probs,
+                            L.at(base, L.iTab), s);
     else if (d.kind)
       e = launch_fwd13d_pass(d, (int)L.nstates, L.S, L.p, state,
                              (last && psi) ? psi : state, stride, W, coef, part, probs, s);

@@ -88,10 +88,13 @@ bool make_plan_reg13(int n, int p, Plan* out);
 // the complex128 gradient, 13 <= n <= 22).
 bool make_plan_reg2set(int n, int p, int K, int C, Plan* out);
 
+// tab: TAB_BYTES of scratch per state for the pass's tile-independent tables
+// (computed by a small kernel launched first on the same stream).
 hipError_t launch_fwd14_pass(const PassDesc& d, int nstates, int S, int p,
                              const void* in, void* out, uint64_t state_stride,
                              const double* W, const LayerCoef* coef,
-                             double* part, void* probs, hipStream_t stream);
+                             double* part, void* probs, void* tab, hipStream_t stream);
+constexpr size_t TAB_BYTES = 8192;
 // complex128 register-tile pass on 13-qubit tiles (kind-2 sets with C = 2).
 hipError_t launch_fwd13d_pass(const PassDesc& d, int nstates, int S, int p,
                               const void* in, void* out, uint64_t state_stride,
@@ -199,7 +202,7 @@ struct Layout {
   size_t state_bytes = 0;  // one state
   Carve cv;
   size_t iW = 0, iC = 0, iPart = 0, iState = 0, iLam = 0, iProbs = 0,
-         iBsum = 0, iBcdf = 0, iCz = 0;
+         iBsum = 0, iBcdf = 0, iCz = 0, iTab = 0;
   std::vector<size_t> iCk;
   int nrec = 0;
   std::vector<int> rec_base;

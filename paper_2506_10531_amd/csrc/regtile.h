@@ -303,15 +303,19 @@ __device__ __forceinline__ double mix_t(const LayerCoef& L, bool inv) {
 
 // Per-tile tables for the phase layout PL (FP64):
 //   Ll[64]    energy of the lane bits alone (with their block fields)
+//   Lw[4]     energy of the wave bits alone (with their block fields)
 //   Gl[R][64] field of the lane bits on register slot s
-//   Lw[4]     energy of the wave bits alone
 //   Fw[6][4]  coupling of lane slot i to the wave bits
 //   Gw[R][4]  field of the wave bits on register slot s
 //   Kr[2^R]   couplings among the register bits
+// Only the first NF entries depend on the tile's block bits; the others, and
+// the factors e^{-i gamma K(r)}, are the same for every tile of a pass and
+// state (they depend on the couplings among the tile's qubits only).
 template <int R>
 struct Tables {
-  double Ll[64], Gl[R][64], Lw[4], Fw[6][4], Gw[R][4], Kr[1 << R];
-  static constexpr int N = 64 + R * 64 + 4 + 6 * 4 + R * 4 + (1 << R);
+  double Ll[64], Lw[4], Gl[R][64], Fw[6][4], Gw[R][4], Kr[1 << R];
+  static constexpr int NF = 64 + 4;
+  static constexpr int N = NF + R * 64 + 6 * 4 + R * 4 + (1 << R);
 };
 
 // 0.0 or 1.0: bit i of x.  Table sums multiply by it instead of branching,
@@ -339,6 +343,13 @@ __device__ __forceinline__ void table_entry(Tables<G::R>* T, const double* fl, c
     return;
   }
   e -= 64;
+  if (e < 4) {
+    const int b0 = G::wave_bit(PL, 0), b1 = G::wave_bit(PL, 1);
+    const double t1 = fl[b1] + bitd(e, 0) * Wl[b1 * K + b0];
+    T->Lw[e] = fma(bitd(e, 0), fl[b0], bitd(e, 1) * t1);
+    return;
+  }
+  e -= 4;
   if (e < R * 64) {
     const int sl = e >> 6, x = e & 63, br = G::reg_bit(PL, sl);
     double s = 0.0;
@@ -348,13 +359,6 @@ __device__ __forceinline__ void table_entry(Tables<G::R>* T, const double* fl, c
     return;
   }
   e -= R * 64;
-  if (e < 4) {
-    const int b0 = G::wave_bit(PL, 0), b1 = G::wave_bit(PL, 1);
-    const double t1 = fl[b1] + bitd(e, 0) * Wl[b1 * K + b0];
-    T->Lw[e] = fma(bitd(e, 0), fl[b0], bitd(e, 1) * t1);
-    return;
-  }
-  e -= 4;
   if (e < 6 * 4) {
     const int li = e >> 2, y = e & 3, bl = G::lane_bit(PL, li);
     T->Fw[li][y] = fma(bitd(y, 0), Wl[bl * K + G::wave_bit(PL, 0)],
@@ -578,6 +582,20 @@ __device__ __forceinline__ uint64_t tile_base(uint64_t ti, int kind, int a) {
   return ((ti & ((1ull << gap) - 1ull)) << C) | ((ti >> gap) << (a + K - C));
 }
 
+// Couplings Wl[K][K] among the tile bits (the same for every tile of a set),
+// with the signs of tile bit 0's couplings flipped when f0.
+template <int K, int C, int KIND>
+__device__ __forceinline__ void tile_couplings(const double* Wsh, int n, int a, bool f0,
+                                               double* Wl, int tid) {
+  for (int e = tid; e < K * K; e += NT) {
+    const int i = e / K, j = e - K * i;
+    const int pi = (KIND == 1 || i < C) ? i : a + i - C;
+    const int pj = (KIND == 1 || j < C) ? j : a + j - C;
+    const double w = (i == j) ? 0.0 : Wsh[pi * n + pj];
+    Wl[e] = (f0 && (i == 0) != (j == 0)) ? -w : w;
+  }
+}
+
 // LDS context of one tile: the folded Q staged in LDS (Wsh, n x n), the
 // tile-local fields fl[K] (block fields on the tile bits), couplings Wl[K][K]
 // among tile bits and the energy of the block bits (returned).  With f0, the
@@ -607,17 +625,27 @@ __device__ __forceinline__ double tile_context(const double* Wsh, int n, int a, 
     for (int j = 0; j < cnt; ++j) t = fma(bitd(zb, j), Wsh[row * n + j], t);
     tmp[i] = fr ? (f0 ? t : 0.0) : bitd(zb, i) * t;
   }
-  for (int e = tid; e < K * K; e += NT) {
-    const int i = e / K, j = e - K * i;
-    const int pi = (KIND == 1 || i < C) ? i : a + i - C;
-    const int pj = (KIND == 1 || j < C) ? j : a + j - C;
-    const double w = (i == j) ? 0.0 : Wsh[pi * n + pj];
-    Wl[e] = (f0 && (i == 0) != (j == 0)) ? -w : w;
-  }
+  tile_couplings<K, C, KIND>(Wsh, n, a, f0, Wl, tid);
   lds_barrier();
   double cblk = 0.0;
   for (int i = 0; i <= n; ++i) cblk += tmp[i];
   return cblk;
+}
+
+// e^{-i 2 pi gp K(r)} for the couplings K(r) among the register bits r.
+template <class G, int PL>
+__device__ __forceinline__ typename G::V reg_factor(const double* Wl, double gp, int r) {
+  constexpr int R = G::R, K = Dim<G>::K;
+  double k = 0.0;
+#pragma unroll
+  for (int i = 1; i < R; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < i; ++j) t = fma(bitd(r, j), Wl[G::reg_bit(PL, i) * K + G::reg_bit(PL, j)], t);
+    k = fma(bitd(r, i), t, k);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  return unitv<typename G::V>(gp * k);
 }
 
 // Tables of layout PL and the per-tile factors KF[r] = e^{-i 2 pi gp K(r)}
@@ -628,19 +656,7 @@ __device__ __forceinline__ void tile_tables(Tables<G::R>* T, typename G::V* KF, 
   constexpr int R = G::R, K = Dim<G>::K;
 #pragma unroll 1
   for (int e = tid; e < Tables<R>::N; e += NT) table_entry<G, PL>(T, fl, Wl, e);
-  if (kf && tid < (1 << R)) {
-    double k = 0.0;
-#pragma unroll
-    for (int i = 1; i < R; ++i) {
-      double t = 0.0;
-#pragma unroll
-      for (int j = 0; j < i; ++j)
-        t = fma(bitd(tid, j), Wl[G::reg_bit(PL, i) * K + G::reg_bit(PL, j)], t);
-      k = fma(bitd(tid, i), t, k);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    KF[tid] = unitv<typename G::V>(gp * k);
-  }
+  if (kf && tid < (1 << R)) KF[tid] = reg_factor<G, PL>(Wl, gp, tid);
   lds_barrier();
 }
 
@@ -648,16 +664,28 @@ __device__ __forceinline__ void tile_tables(Tables<G::R>* T, typename G::V* KF, 
 // the tile's loads are in flight: the Q reads are issued first, then issue(),
 // the tile loads, then the LDS writes wait for the Q reads only.  Ends with a
 // barrier.
-template <class Issue>
+struct NoCopy {
+  __device__ double operator()(int) const { return 0.0; }
+  __device__ void operator()(int, double) const {}
+};
+template <int NX = 0, class Issue, class Src = NoCopy, class Dst = NoCopy>
 __device__ __forceinline__ void stage_context(const double* W, int n, const LayerCoef* coef, int p,
-                                              double* Wsh, LayerCoef* cf, int tid, Issue&& issue) {
+                                              double* Wsh, LayerCoef* cf, int tid, Issue&& issue,
+                                              Src&& src = Src(), Dst&& dst = Dst()) {
   constexpr int NW = (34 * 34 + NT - 1) / NT;
+  constexpr int NXT = (NX + NT - 1) / NT;  // extra words per thread (NX words in all)
   const int nn = n * n;
   double wr[NW];
+  double xr[NXT > 0 ? NXT : 1];
 #pragma unroll
   for (int k = 0; k < NW; ++k) {
     const int e = tid + k * NT;
     wr[k] = e < nn ? W[e] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < NXT; ++k) {
+    const int e = tid + k * NT;
+    xr[k] = e < NX ? src(e) : 0.0;
   }
   static_assert(sizeof(LayerCoef) == 40, "layer coefficients move as five doubles");
   double cv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -673,6 +701,11 @@ __device__ __forceinline__ void stage_context(const double* W, int n, const Laye
   for (int k = 0; k < NW; ++k) {
     const int e = tid + k * NT;
     if (e < nn) Wsh[e] = wr[k];
+  }
+#pragma unroll
+  for (int k = 0; k < NXT; ++k) {
+    const int e = tid + k * NT;
+    if (e < NX) dst(e, xr[k]);
   }
   if (tid < p) {
     double* c = reinterpret_cast<double*>(cf + tid);
@@ -703,7 +736,39 @@ struct FwdArgs {
   const LayerCoef* coef;
   double* part;
   void* probs;      // |psi|^2 in the state precision
+  const void* tab = nullptr;  // per-state PassTab of the pass (PRE kernels)
 };
+
+// The tile-independent part of a pass's tables for one state: Tables
+// entries [NF, N) and, for passes with a phase, the register factors.
+template <class G>
+struct PassTab {
+  Tables<G::R> T;
+  typename G::V KF[1 << G::R];
+};
+
+// One work-group per state: the PassTab of pass A.d (kind KIND) for state
+// blockIdx.x, from the folded Q and the state's layer coefficients.
+template <class G, int KIND>
+__global__ void __launch_bounds__(NT) pass_tables_kernel(FwdArgs A, PassTab<G>* out) {
+  constexpr int K = Dim<G>::K, R = G::R, PL = G::template PL<KIND>;
+  __shared__ double Wsh[34 * 34];
+  __shared__ double Wl[K * K];
+  __shared__ LayerCoef cf[64];
+  const PassDesc& d = A.d;
+  const int tid = threadIdx.x, n = d.n, st = blockIdx.x;
+  const double* W = A.W + (size_t)(st / A.S) * n * n;
+  for (int e = tid; e < n * n; e += NT) Wsh[e] = W[e];
+  if (tid < A.p) cf[tid] = A.coef[(size_t)st * A.p + tid];
+  lds_barrier();
+  // the same flip of tile bit 0 as the pass (set 0 after a cot-form lead)
+  const bool f0 = KIND == 1 && d.lead >= 0 && cf[d.lead].mode != 0;
+  tile_couplings<K, G::C, KIND>(Wsh, n, d.a, f0, Wl, tid);
+  lds_barrier();
+  PassTab<G>* o = out + st;
+  for (int e = Tables<R>::NF + tid; e < Tables<R>::N; e += NT) table_entry<G, PL>(&o->T, nullptr, Wl, e);
+  if (d.ja <= d.jb && tid < (1 << R)) o->KF[tid] = reg_factor<G, PL>(Wl, cf[d.jb].gp, tid);
+}
 
 // Pass shape of a descriptor, or -1.
 inline int pass_shape(const PassDesc& d, int p) {
@@ -738,7 +803,7 @@ __device__ __forceinline__ uint64_t xcd_tile() {
 // pass shape keeps the tile's registers in place from load to store.  With
 // TRUE_OUT a stored state carries its pending mixer scalar (the adjoint
 // passes read such states).
-template <class G, int KIND, int MIXLO, int PT, bool TRUE_OUT = false>
+template <class G, int KIND, int MIXLO, int PT, bool TRUE_OUT = false, bool PRE = false>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
 fwd_kernel(FwdArgs A) {
   using D = Dim<G>;
@@ -764,13 +829,32 @@ fwd_kernel(FwdArgs A) {
   V* const gout = reinterpret_cast<V*>(A.out) + st * A.stride + zb;
   double* const Wsh = reinterpret_cast<double*>(buf);  // idle until the first transpose
   V v[NA];
-  stage_context(A.W + (size_t)(st / A.S) * n * n, n, A.coef + st * A.p, A.p, Wsh, cf, tid, [&] {
-    if (PT != P_FIRST) load_tile<G, LA>(v, gin, lane, wave, KIND, d.a);
-  });
+  // PRE: the tile-independent tables come from the state's PassTab, copied
+  // to LDS with the folded Q while the tile is in flight
+  constexpr int NT1 = Tables<G::R>::N - Tables<G::R>::NF;
+  constexpr int NT2 = PRE && PHASE ? (int)(sizeof(V) << G::R) / 8 : 0;
+  const PassTab<G>* tab = reinterpret_cast<const PassTab<G>*>(A.tab) + st;
+  stage_context<(PRE && PT != P_LEAD) ? NT1 + NT2 : 0>(
+      A.W + (size_t)(st / A.S) * n * n, n, A.coef + st * A.p, A.p, Wsh, cf, tid,
+      [&] {
+        if (PT != P_FIRST) load_tile<G, LA>(v, gin, lane, wave, KIND, d.a);
+      },
+      [&](int w) {
+        return w < NT1 ? (&tab->T.Gl[0][0])[w] : reinterpret_cast<const double*>(tab->KF)[w - NT1];
+      },
+      [&](int w, double x) {
+        if (w < NT1) (&T.Gl[0][0])[w] = x;
+        else reinterpret_cast<double*>(KF)[w - NT1] = x;
+      });
   // tile bit 0 flipped at PL (only when the pass mixes bit 0)
   const bool f0 = MIXLO == 0 && LEAD && cf[d.lead].mode != 0;
   const double cblk = tile_context<K, G::C, KIND>(Wsh, n, d.a, zb, f0, fl, Wl, tmp, tid);
-  if (PT != P_LEAD) tile_tables<G, PL>(&T, KF, fl, Wl, PHASE, PHASE ? cf[d.jb].gp : 0.0, tid);
+  if (PRE && PT != P_LEAD) {
+    for (int e = tid; e < Tables<G::R>::NF; e += NT) table_entry<G, PL>(&T, fl, Wl, e);
+    lds_barrier();
+  } else if (PT != P_LEAD) {
+    tile_tables<G, PL>(&T, KF, fl, Wl, PHASE, PHASE ? cf[d.jb].gp : 0.0, tid);
+  }
 
   // pending mixer scalar (at the phase, or at the outputs of the last pass)
   double sr = 1.0, si = 0.0;
