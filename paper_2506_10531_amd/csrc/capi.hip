@@ -426,7 +426,8 @@ int run_forward(const Layout& L, char* base, const double* Q,
                             L.at(base, L.iTab), s);
     else if (d.kind)
       e = launch_fwd13d_pass(d, (int)L.nstates, L.S, L.p, state,
-                             (last && psi) ? psi : state, stride, W, coef, part, probs, s);
+                             (last && psi) ? psi : state, stride, W, coef, part, probs,
+                             L.at(base, L.iTab), s);
     else
       e = launch_fwd_pass(L.prec, d, (int)L.nstates, L.S, L.p, state,
                           (last && psi) ? psi : state, stride, W, coef, part, probs, s);
@@ -488,6 +489,7 @@ int enqueue_grad(const Layout& L, char* base, const double* Q,
   const uint64_t stride = 1ull << L.n;
   const double sb = (double)L.state_bytes * L.nstates;
   auto ck = [&](int i) { return (void*)L.at(base, L.iCk[i]); };
+  void* const tab = L.at(base, L.iTab);
   void* lam = np > 1 ? (void*)L.at(base, L.iLam) : nullptr;
   if ((P.K == 13 || P.K == 12) && P.pass[0].kind != 0) {
     const bool c128 = P.K == 12;
@@ -497,9 +499,9 @@ int enqueue_grad(const Layout& L, char* base, const double* Q,
       PassDesc d = P.pass[i];
       TimerScope ts(tm, s, (i == 0 ? 0.0 : sb) + sb);
       e = c128 ? launch_fwd12_ckpt_pass(d, ns, S, p, i ? ck(i - 1) : nullptr, ck(i), stride, W,
-                                        coef, s)
+                                        coef, tab, s)
                : launch_fwd13_ckpt_pass(d, ns, S, p, i ? ck(i - 1) : nullptr, ck(i), stride, W,
-                                        coef, s);
+                                        coef, tab, s);
       if (e != hipSuccess) return hip_error(e, "checkpoint pass");
     }
     for (int i = np - 1; i >= 0; --i) {
@@ -507,7 +509,7 @@ int enqueue_grad(const Layout& L, char* base, const double* Q,
       TimerScope ts(tm, s, (shape == 1 ? 3 : 2) * sb);
       e = (c128 ? launch_bwd12_pass : launch_bwd13_pass)(
           P.pass[i], shape, ns, S, p, ck(i == np - 1 ? i - 1 : i), lam, stride, W, coef, part,
-          L.rec_base[i], L.nrec, s);
+          L.rec_base[i], L.nrec, tab, s);
       if (e != hipSuccess) return hip_error(e, "adjoint pass");
     }
     double* outs[3] = {dgamma, dbeta, expect};

@@ -23,7 +23,7 @@ using G13D = G13T<double2, double, 2>;
 
 hipError_t launch_fwd13d_pass(const PassDesc& d, int nstates, int S, int p, const void* in,
                               void* out, uint64_t state_stride, const double* W,
-                              const LayerCoef* coef, double* part, void* probs,
+                              const LayerCoef* coef, double* part, void* probs, void* tab,
                               hipStream_t stream) {
   if (d.n < 14 || d.n > 34 || d.k != 13 || p < 1 || p > 64 || nstates < 1 || S < 1)
     return hipErrorInvalidValue;
@@ -43,10 +43,19 @@ hipError_t launch_fwd13d_pass(const PassDesc& d, int nstates, int S, int p, cons
   A.coef = coef;
   A.part = part;
   A.probs = probs;
+  A.tab = tab;
   const uint64_t total = (uint64_t)nstates << (d.n - 13);
   if (total > 0xFFFFFFFFull) return hipErrorInvalidValue;
   const dim3 grid((unsigned)total), blk(NT);
-#define DQ_K(K, M, T) hipLaunchKernelGGL((fwd_kernel<G13D, K, M, T>), grid, blk, 0, stream, A)
+  if (pt != P_LEAD) {
+    // the tile-independent tables of every state, then the pass
+    const hipError_t e = d.kind == 1
+        ? launch_pass_tables<G13D, 1>(d, nstates, S, p, W, coef, fwd_tab_spec(d), tab, stream)
+        : launch_pass_tables<G13D, 2>(d, nstates, S, p, W, coef, fwd_tab_spec(d), tab, stream);
+    if (e != hipSuccess) return e;
+  }
+#define DQ_K(K, M, T) \
+  hipLaunchKernelGGL((fwd_kernel<G13D, K, M, T, false, true>), grid, blk, 0, stream, A)
 #define DQ_PT(K, M)                         \
   switch (pt) {                             \
     case P_MID: DQ_K(K, M, P_MID); break;   \

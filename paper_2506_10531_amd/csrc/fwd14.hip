@@ -133,7 +133,6 @@ hipError_t launch_fwd14_pass(const PassDesc& d, int nstates, int S, int p,
                              double* part, void* probs, void* tab, hipStream_t stream) {
   if (d.n < 15 || d.n > 34 || p < 1 || p > 64 || nstates < 1 || S < 1)
     return hipErrorInvalidValue;
-  static_assert(sizeof(PassTab<G14T<4>>) <= TAB_BYTES, "pass tables exceed their scratch");
   const int pt = pass_shape(d, p);
   if (pt < 0 || (d.kind == 1 && pt == P_LEAD)) return hipErrorInvalidValue;
   if (d.kind == 1 ? d.mixlo != 0 : (d.mixlo < 4 || d.mixlo > 13)) return hipErrorInvalidValue;
@@ -155,19 +154,15 @@ hipError_t launch_fwd14_pass(const PassDesc& d, int nstates, int S, int p,
   const dim3 grid((unsigned)total), blk(NT);
   if (pt != P_LEAD) {
     // the tile-independent tables of every state, then the pass
-    if (!tab) return hipErrorInvalidValue;
-    const int c = d.kind == 1 ? 4 : d.c;
-#define DQ_T(KK, CC)                                                                         \
-  hipLaunchKernelGGL((pass_tables_kernel<G14T<CC>, KK>), dim3(nstates), blk, 0, stream, A, \
-                     reinterpret_cast<PassTab<G14T<CC>>*>(tab))
-    if (d.kind == 1) DQ_T(1, 4);
-    else if (c == 4) DQ_T(2, 4);
-    else if (c == 5) DQ_T(2, 5);
-    else if (c == 6) DQ_T(2, 6);
-    else if (c == 7) DQ_T(2, 7);
-    else DQ_T(2, 8);
+    const TabSpec ts = fwd_tab_spec(d);
+#define DQ_T(KK, CC) launch_pass_tables<G14T<CC>, KK>(d, nstates, S, p, W, coef, ts, tab, stream)
+    const hipError_t e = d.kind == 1 ? DQ_T(1, 4)
+                         : d.c == 4  ? DQ_T(2, 4)
+                         : d.c == 5  ? DQ_T(2, 5)
+                         : d.c == 6  ? DQ_T(2, 6)
+                         : d.c == 7  ? DQ_T(2, 7)
+                                     : DQ_T(2, 8);
 #undef DQ_T
-    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
 #define DQ_K(K, M, T)                                                                        \

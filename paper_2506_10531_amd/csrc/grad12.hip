@@ -19,7 +19,7 @@ using G12D = G12T<double2, double, 2>;
 
 hipError_t launch_fwd12_ckpt_pass(const PassDesc& d, int nstates, int S, int p, const void* in,
                                   void* out, uint64_t stride, const double* W,
-                                  const LayerCoef* coef, hipStream_t stream) {
+                                  const LayerCoef* coef, void* tab, hipStream_t stream) {
   if (d.n < 13 || d.n > 22 || p < 1 || p > 64 || nstates < 1 || S < 1) return hipErrorInvalidValue;
   const int pt = pass_shape(d, p);
   if (pt != P_FIRST && pt != P_MID) return hipErrorInvalidValue;
@@ -33,11 +33,19 @@ hipError_t launch_fwd12_ckpt_pass(const PassDesc& d, int nstates, int S, int p, 
   A.stride = stride;
   A.W = W;
   A.coef = coef;
+  A.tab = tab;
   const uint64_t total = (uint64_t)nstates << (d.n - 12);
   if (total > 0xFFFFFFFFull) return hipErrorInvalidValue;
   const dim3 grid((unsigned)total), blk(NT);
+  {
+    // the tile-independent tables of every state, then the pass
+    const hipError_t e = d.kind == 1
+        ? launch_pass_tables<G12D, 1>(d, nstates, S, p, W, coef, fwd_tab_spec(d), tab, stream)
+        : launch_pass_tables<G12D, 2>(d, nstates, S, p, W, coef, fwd_tab_spec(d), tab, stream);
+    if (e != hipSuccess) return e;
+  }
 #define DQ_K(K, M, T) \
-  hipLaunchKernelGGL((fwd_kernel<G12D, K, M, T, true>), grid, blk, 0, stream, A)
+  hipLaunchKernelGGL((fwd_kernel<G12D, K, M, T, true, true>), grid, blk, 0, stream, A)
   if (d.kind == 1) {
     if (pt == P_FIRST) DQ_K(1, 0, P_FIRST);
     else DQ_K(1, 0, P_MID);
@@ -62,7 +70,7 @@ hipError_t launch_fwd12_ckpt_pass(const PassDesc& d, int nstates, int S, int p, 
 hipError_t launch_bwd12_pass(const PassDesc& d, int shape, int nstates, int S, int p,
                              const void* psi, void* lam, uint64_t stride, const double* W,
                              const LayerCoef* coef, double* part, int rec_base, int nrec,
-                             hipStream_t stream) {
+                             void* tab, hipStream_t stream) {
   if (d.n < 13 || d.n > 22 || p < 1 || p > 64 || nstates < 1 || S < 1) return hipErrorInvalidValue;
   if (d.kind == 1 ? d.mixlo != 0 : (d.mixlo < 2 || d.mixlo > 11)) return hipErrorInvalidValue;
   const bool phase = d.ja <= d.jb;
@@ -92,10 +100,22 @@ hipError_t launch_bwd12_pass(const PassDesc& d, int shape, int nstates, int S, i
   A.part = part;
   A.rec_base = rec_base;
   A.nrec = nrec;
+  A.tab = tab;
   const uint64_t total = (uint64_t)nstates << (d.n - 12);
   if (total > 0xFFFFFFFFull) return hipErrorInvalidValue;
   const dim3 grid((unsigned)total), blk(NT);
-#define DQ_B(K, M, T) hipLaunchKernelGGL((bwd_kernel<G12D, K, M, T>), grid, blk, 0, stream, A)
+  {
+    // the tile-independent tables of every state, then the pass: the undone
+    // half-mixer at the phase layout flips bit 0, the middle shape undoes a phase
+    const TabSpec ts{d.kind == 1 ? (shape == B_SEED ? d.lead : d.jb) : -1,
+                     shape == B_MID ? d.jb : -1, -1.0};
+    const hipError_t e = d.kind == 1
+        ? launch_pass_tables<G12D, 1>(d, nstates, S, p, W, coef, ts, tab, stream)
+        : launch_pass_tables<G12D, 2>(d, nstates, S, p, W, coef, ts, tab, stream);
+    if (e != hipSuccess) return e;
+  }
+#define DQ_B(K, M, T) \
+  hipLaunchKernelGGL((bwd_kernel<G12D, K, M, T, true>), grid, blk, 0, stream, A)
 #define DQ_BT(K, M)                   \
   switch (shape) {                    \
     case B_SEED: DQ_B(K, M, B_SEED); break; \

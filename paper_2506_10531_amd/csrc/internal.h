@@ -99,27 +99,27 @@ constexpr size_t TAB_BYTES = 8192;
 hipError_t launch_fwd13d_pass(const PassDesc& d, int nstates, int S, int p,
                               const void* in, void* out, uint64_t state_stride,
                               const double* W, const LayerCoef* coef,
-                              double* part, void* probs, hipStream_t stream);
+                              double* part, void* probs, void* tab, hipStream_t stream);
 // Gradient passes on 13-qubit register tiles (complex64).  The checkpoint
 // pass (first or middle shape) stores its output with every mixer scalar
 // applied; the backward shapes are 0 = seed (the last forward pass fused with
 // its adjoint), 1 = middle, 2 = first.
 hipError_t launch_fwd13_ckpt_pass(const PassDesc& d, int nstates, int S, int p, const void* in,
                                   void* out, uint64_t stride, const double* W,
-                                  const LayerCoef* coef, hipStream_t stream);
+                                  const LayerCoef* coef, void* tab, hipStream_t stream);
 hipError_t launch_bwd13_pass(const PassDesc& d, int shape, int nstates, int S, int p,
                              const void* psi, void* lam, uint64_t stride, const double* W,
                              const LayerCoef* coef, double* part, int rec_base, int nrec,
-                             hipStream_t stream);
+                             void* tab, hipStream_t stream);
 // Gradient passes on 12-qubit register tiles (complex128), as the 13-qubit
 // complex64 ones: 13 <= n <= 22, kind-2 sets with 2 low bits.
 hipError_t launch_fwd12_ckpt_pass(const PassDesc& d, int nstates, int S, int p, const void* in,
                                   void* out, uint64_t stride, const double* W,
-                                  const LayerCoef* coef, hipStream_t stream);
+                                  const LayerCoef* coef, void* tab, hipStream_t stream);
 hipError_t launch_bwd12_pass(const PassDesc& d, int shape, int nstates, int S, int p,
                              const void* psi, void* lam, uint64_t stride, const double* W,
                              const LayerCoef* coef, double* part, int rec_base, int nrec,
-                             hipStream_t stream);
+                             void* tab, hipStream_t stream);
 
 // ---- launchers (kernels.hip) ---------------------------------------------
 // prec: 0 = complex128, 1 = complex64.

@@ -747,27 +747,54 @@ struct PassTab {
   typename G::V KF[1 << G::R];
 };
 
-// One work-group per state: the PassTab of pass A.d (kind KIND) for state
+// Which layer coefficients a pass's tables use: the cot form of layer
+// flip_layer flips tile bit 0 (set 0 only; -1: no flip), and the register
+// factors are e^{-i 2 pi kf_sign gp K(r)} with gp of layer kf_layer (-1: none).
+struct TabSpec {
+  int flip_layer;
+  int kf_layer;
+  double kf_sign;
+};
+
+// One work-group per state: the PassTab of pass d (kind KIND) for state
 // blockIdx.x, from the folded Q and the state's layer coefficients.
 template <class G, int KIND>
-__global__ void __launch_bounds__(NT) pass_tables_kernel(FwdArgs A, PassTab<G>* out) {
+__global__ void __launch_bounds__(NT) pass_tables_kernel(PassDesc d, int S, int p,
+                                                         const double* W, const LayerCoef* coef,
+                                                         TabSpec spec, PassTab<G>* out) {
   constexpr int K = Dim<G>::K, R = G::R, PL = G::template PL<KIND>;
   __shared__ double Wsh[34 * 34];
   __shared__ double Wl[K * K];
   __shared__ LayerCoef cf[64];
-  const PassDesc& d = A.d;
   const int tid = threadIdx.x, n = d.n, st = blockIdx.x;
-  const double* W = A.W + (size_t)(st / A.S) * n * n;
-  for (int e = tid; e < n * n; e += NT) Wsh[e] = W[e];
-  if (tid < A.p) cf[tid] = A.coef[(size_t)st * A.p + tid];
+  const double* Ws = W + (size_t)(st / S) * n * n;
+  for (int e = tid; e < n * n; e += NT) Wsh[e] = Ws[e];
+  if (tid < p) cf[tid] = coef[(size_t)st * p + tid];
   lds_barrier();
-  // the same flip of tile bit 0 as the pass (set 0 after a cot-form lead)
-  const bool f0 = KIND == 1 && d.lead >= 0 && cf[d.lead].mode != 0;
+  const bool f0 = KIND == 1 && spec.flip_layer >= 0 && cf[spec.flip_layer].mode != 0;
   tile_couplings<K, G::C, KIND>(Wsh, n, d.a, f0, Wl, tid);
   lds_barrier();
   PassTab<G>* o = out + st;
   for (int e = Tables<R>::NF + tid; e < Tables<R>::N; e += NT) table_entry<G, PL>(&o->T, nullptr, Wl, e);
-  if (d.ja <= d.jb && tid < (1 << R)) o->KF[tid] = reg_factor<G, PL>(Wl, cf[d.jb].gp, tid);
+  if (spec.kf_layer >= 0 && tid < (1 << R))
+    o->KF[tid] = reg_factor<G, PL>(Wl, spec.kf_sign * cf[spec.kf_layer].gp, tid);
+}
+
+// Queue pass_tables_kernel for nstates states (tab: nstates records).
+template <class G, int KIND>
+inline hipError_t launch_pass_tables(const PassDesc& d, int nstates, int S, int p,
+                                     const double* W, const LayerCoef* coef, TabSpec spec,
+                                     void* tab, hipStream_t stream) {
+  static_assert(sizeof(PassTab<G>) <= TAB_BYTES, "pass tables exceed their scratch");
+  if (!tab || nstates < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((pass_tables_kernel<G, KIND>), dim3(nstates), dim3(NT), 0, stream, d, S, p,
+                     W, coef, spec, reinterpret_cast<PassTab<G>*>(tab));
+  return hipGetLastError();
+}
+
+// The forward pass's spec: its lead flips bit 0, its phase layer gives KF.
+inline TabSpec fwd_tab_spec(const PassDesc& d) {
+  return TabSpec{d.kind == 1 && d.lead >= 0 ? d.lead : -1, d.ja <= d.jb ? d.jb : -1, 1.0};
 }
 
 // Pass shape of a descriptor, or -1.
