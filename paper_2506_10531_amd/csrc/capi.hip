@@ -142,7 +142,7 @@ bool make_plan(int n, int p, int kmax, int cpref, Plan* P) {
 // into runs of at most K - C, and set i's tile is the C low bits plus the
 // (K - C)-bit run [a, a + K - C) that ends at its mixed run (or at n), so it
 // carries (does not mix) any of those bits below its own run.
-bool make_plan_regtile(int n, int p, int K, int C, Plan* P, int cmax) {
+bool make_plan_regtile(int n, int p, int K, int C, Plan* P, int cmax, bool rev) {
   *P = Plan();
   P->K = K;
   const int span = K - C;
@@ -193,7 +193,9 @@ bool make_plan_regtile(int n, int p, int K, int C, Plan* P, int cmax) {
     }
     return d;
   };
-  auto order = [&](int j, int i) { return (j % 2 == 0) ? i : m - 1 - i; };
+  // the set that finishes layer j's mixer starts layer j + 1; rev starts the
+  // first layer on the last set instead of set 0
+  auto order = [&](int j, int i) { return ((j % 2 == 0) != rev) ? i : m - 1 - i; };
   int np = 0;
   P->pass[np++] = desc(order(0, 0), -1, 0, 0);
   for (int j = 0; j < p; ++j) {
@@ -227,8 +229,12 @@ bool make_plan_regtile(int n, int p, int K, int C, Plan* P, int cmax) {
   return true;
 }
 
+// Starts on the last set: the set-0 passes (14 qubits mixed per half-mixer,
+// contiguous tiles) then take the middle of the plan, where they run faster
+// than the kind-2 ones at n = 24 and 32, and a kind-2 set takes the first
+// (write-only) and last (read-only) passes.
 bool make_plan_reg14(int n, int p, Plan* P) {
-  return n >= 15 && make_plan_regtile(n, p, 14, 4, P, 8);
+  return n >= 15 && make_plan_regtile(n, p, 14, 4, P, 8, true);
 }
 
 bool make_plan_reg2set(int n, int p, int K, int C, Plan* P) {

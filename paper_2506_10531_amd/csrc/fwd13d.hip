@@ -29,6 +29,7 @@ hipError_t launch_fwd13d_pass(const PassDesc& d, int nstates, int S, int p, cons
     return hipErrorInvalidValue;
   const int pt = pass_shape(d, p);
   if (pt < 0 || (d.kind == 1 && pt == P_LEAD)) return hipErrorInvalidValue;
+  if (d.kind == 2 && pt == P_FIRST) return hipErrorInvalidValue;  // set-0 first passes only
   if (d.kind == 1 ? (d.mixlo != 0 || d.c != 13)
                   : (d.c != G13D::C || d.mixlo < 2 || d.mixlo > 12))
     return hipErrorInvalidValue;

@@ -168,11 +168,12 @@ hipError_t launch_fwd14_pass(const PassDesc& d, int nstates, int S, int p,
 #define DQ_K(K, M, T)                                                                        \
   hipLaunchKernelGGL((fwd_kernel<G14T<(K == 1 ? 4 : M < 8 ? M : 8)>, K, M, T, false, true>), \
                      grid, blk, 0, stream, A)
-#define DQ_PT(K, M)                         \
-  switch (pt) {                             \
-    case P_MID: DQ_K(K, M, P_MID); break;   \
-    case P_LEAD: DQ_K(K, M, P_LEAD); break; \
-    default: DQ_K(K, M, P_LAST); break;     \
+#define DQ_PT(K, M)                           \
+  switch (pt) {                               \
+    case P_FIRST: DQ_K(K, M, P_FIRST); break; \
+    case P_MID: DQ_K(K, M, P_MID); break;     \
+    case P_LEAD: DQ_K(K, M, P_LEAD); break;   \
+    default: DQ_K(K, M, P_LAST); break;       \
   }
   if (d.kind == 1) {
     switch (pt) {

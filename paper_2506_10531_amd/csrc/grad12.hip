@@ -23,6 +23,7 @@ hipError_t launch_fwd12_ckpt_pass(const PassDesc& d, int nstates, int S, int p, 
   if (d.n < 13 || d.n > 22 || p < 1 || p > 64 || nstates < 1 || S < 1) return hipErrorInvalidValue;
   const int pt = pass_shape(d, p);
   if (pt != P_FIRST && pt != P_MID) return hipErrorInvalidValue;
+  if (d.kind == 2 && pt == P_FIRST) return hipErrorInvalidValue;  // set-0 first passes only
   if (d.kind == 1 ? d.mixlo != 0 : (d.mixlo < 2 || d.mixlo > 11)) return hipErrorInvalidValue;
   FwdArgs A{};
   A.d = d;

@@ -73,12 +73,13 @@ bool make_plan(int n, int p, int kmax, int cpref, Plan* out);
 // [0, K), set i >= 1 = [0, C_i) + a run of K - C_i high bits of which it mixes
 // its share of [K, n).  The number of sets is that for C_i = C; each set then
 // takes C_i = min(cmax, K - its share).  At most 4 sets, n <= 34.
-bool make_plan_regtile(int n, int p, int K, int C, Plan* out, int cmax);
+bool make_plan_regtile(int n, int p, int K, int C, Plan* out, int cmax, bool rev = false);
 inline bool make_plan_regtile(int n, int p, int K, int C, Plan* out) {
   return make_plan_regtile(n, p, K, C, out, C);
 }
 // complex64 register-tile plan (n >= 15): K = 14, C_i from 4 to 8 (a kind-2
-// set mixing tile bits [MIXLO, 14) has C_i = min(MIXLO, 8)).
+// set mixing tile bits [MIXLO, 14) has C_i = min(MIXLO, 8)); the first layer
+// starts on the last set (rev).
 bool make_plan_reg14(int n, int p, Plan* out);
 // 13-qubit register-tile plan of the complex64 gradient (two sets, 14 <= n
 // <= 22): set 0 = [0, 13), set 1 = [13, n) on tile bits [0, 4) + [a, a + 9).

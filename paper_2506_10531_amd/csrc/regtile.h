@@ -718,7 +718,7 @@ __device__ __forceinline__ void stage_context(const double* W, int n, const Laye
 // ---- forward pass --------------------------------------------------------------
 
 // Pass shapes (every pass of a register-tile plan is one of these):
-//   P_FIRST  initial state, phase, half-mixer PL -> LA, store (set 0)
+//   P_FIRST  initial state, phase, half-mixer PL -> LA, store
 //   P_MID    load, lead half-mixer LA -> PL, phase, half-mixer PL -> LA, store
 //   P_LEAD   load, lead half-mixer LA -> PL, store (sets between the ends of a
 //            layer when there are more than two)
@@ -803,9 +803,7 @@ inline int pass_shape(const PassDesc& d, int p) {
   if (phase && (d.ja != d.jb || d.jb < 0 || d.jb >= p)) return -1;
   if (d.lead >= p) return -1;
   if (d.flags & F_INIT)
-    return (d.lead < 0 && phase && d.kind == 1 && (d.flags & F_WRITE) && !(d.flags & F_REDUCE))
-               ? P_FIRST
-               : -1;
+    return (d.lead < 0 && phase && (d.flags & F_WRITE) && !(d.flags & F_REDUCE)) ? P_FIRST : -1;
   if (d.lead < 0) return -1;
   if (d.flags & F_REDUCE) return phase ? -1 : P_LAST;
   if (!(d.flags & F_WRITE)) return -1;
