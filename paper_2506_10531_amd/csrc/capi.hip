@@ -325,7 +325,9 @@ static bool use_reg13d(int op, int prec, int n) {
 
 bool choose_plan(int op, int prec, int n, int p, Plan* P) {
   if (use_reg14(op, prec, n)) return make_plan_reg14(n, p, P);
-  if (use_reg13d(op, prec, n)) return make_plan_regtile(n, p, 13, 2, P);
+  // complex128 forward: 13-qubit tiles, 2 contiguous low qubits in the other
+  // sets, first layer on the last set (as the complex64 plan)
+  if (use_reg13d(op, prec, n)) return make_plan_regtile(n, p, 13, 2, P, 2, true);
   if (use_reg13(op, prec, n)) return make_plan_reg13(n, p, P);
   if (use_reg12(op, prec, n)) return make_plan_reg2set(n, p, 12, 2, P);
   return make_plan(n, p, kmax_for(prec, op == OP_GRAD), cpref_for(prec), P);

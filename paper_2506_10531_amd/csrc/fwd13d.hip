@@ -29,7 +29,6 @@ hipError_t launch_fwd13d_pass(const PassDesc& d, int nstates, int S, int p, cons
     return hipErrorInvalidValue;
   const int pt = pass_shape(d, p);
   if (pt < 0 || (d.kind == 1 && pt == P_LEAD)) return hipErrorInvalidValue;
-  if (d.kind == 2 && pt == P_FIRST) return hipErrorInvalidValue;  // set-0 first passes only
   if (d.kind == 1 ? (d.mixlo != 0 || d.c != 13)
                   : (d.c != G13D::C || d.mixlo < 2 || d.mixlo > 12))
     return hipErrorInvalidValue;
@@ -57,11 +56,12 @@ hipError_t launch_fwd13d_pass(const PassDesc& d, int nstates, int S, int p, cons
   }
 #define DQ_K(K, M, T) \
   hipLaunchKernelGGL((fwd_kernel<G13D, K, M, T, false, true>), grid, blk, 0, stream, A)
-#define DQ_PT(K, M)                         \
-  switch (pt) {                             \
-    case P_MID: DQ_K(K, M, P_MID); break;   \
-    case P_LEAD: DQ_K(K, M, P_LEAD); break; \
-    default: DQ_K(K, M, P_LAST); break;     \
+#define DQ_PT(K, M)                           \
+  switch (pt) {                               \
+    case P_FIRST: DQ_K(K, M, P_FIRST); break; \
+    case P_MID: DQ_K(K, M, P_MID); break;     \
+    case P_LEAD: DQ_K(K, M, P_LEAD); break;   \
+    default: DQ_K(K, M, P_LAST); break;       \
   }
   if (d.kind == 1) {
     switch (pt) {
