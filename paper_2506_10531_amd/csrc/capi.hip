@@ -237,11 +237,14 @@ bool make_plan_reg14(int n, int p, Plan* P) {
   return n >= 15 && make_plan_regtile(n, p, 14, 4, P, 8, true);
 }
 
-bool make_plan_reg2set(int n, int p, int K, int C, Plan* P) {
+bool make_plan_reg2set(int n, int p, int K, int C, Plan* P, int cmax) {
   *P = Plan();
   const int span = K - C;
-  if (n <= K || n > K + span || p < 1 || p > 64) return false;
-  const int a = n - span < C ? C : n - span;
+  if (n <= K || n > K + span || p < 1 || p > 64 || cmax < C || cmax >= K) return false;
+  // the second set keeps min(cmax, K - (n - K)) contiguous low tile bits: its
+  // run of high tile bits is exactly qubits [K, n) unless capped
+  const int C1 = 2 * K - n < cmax ? 2 * K - n : cmax;
+  const int a = n - (K - C1);
   P->K = K;
   P->sets = 2;
   P->c = C;
@@ -262,9 +265,9 @@ bool make_plan_reg2set(int n, int p, int K, int C, Plan* P) {
       d.mixlo = 0;
       d.kind = 1;
     } else {
-      d.c = C;
+      d.c = C1;
       d.a = a;
-      d.mixlo = C + (K - a);
+      d.mixlo = C1 + (K - a);
       d.kind = 2;
     }
     return d;
@@ -283,7 +286,7 @@ bool make_plan_reg2set(int n, int p, int K, int C, Plan* P) {
 }
 
 bool make_plan_reg13(int n, int p, Plan* P) {
-  return n >= 14 && n <= 22 && make_plan_reg2set(n, p, 13, 4, P);
+  return n >= 14 && n <= 22 && make_plan_reg2set(n, p, 13, 4, P, 8);
 }
 
 static bool grad_reg_off() {

@@ -28,7 +28,24 @@ namespace {
 
 using namespace rt;
 
-using G13 = G13T<float2, float, 4>;
+// C: contiguous low tile bits of the second set, min(MIXLO, 8) (its run of
+// high tile bits is exactly its qubits)
+template <int C>
+using G13C = G13T<float2, float, C>;
+using G13 = G13C<4>;
+
+// The pass tables for kind KK (kind-2 geometry by the pass's C).
+inline hipError_t g13_tables(const PassDesc& d, int nstates, int S, int p, const double* W,
+                             const LayerCoef* coef, TabSpec ts, void* tab, hipStream_t stream) {
+#define DQ_T(KK, CC) launch_pass_tables<G13C<CC>, KK>(d, nstates, S, p, W, coef, ts, tab, stream)
+  return d.kind == 1 ? DQ_T(1, 4)
+         : d.c == 4  ? DQ_T(2, 4)
+         : d.c == 5  ? DQ_T(2, 5)
+         : d.c == 6  ? DQ_T(2, 6)
+         : d.c == 7  ? DQ_T(2, 7)
+                     : DQ_T(2, 8);
+#undef DQ_T
+}
 
 }  // namespace
 
@@ -40,6 +57,7 @@ hipError_t launch_fwd13_ckpt_pass(const PassDesc& d, int nstates, int S, int p, 
   if (pt != P_FIRST && pt != P_MID) return hipErrorInvalidValue;
   if (d.kind == 2 && pt == P_FIRST) return hipErrorInvalidValue;  // set-0 first passes only
   if (d.kind == 1 ? d.mixlo != 0 : (d.mixlo < 4 || d.mixlo > 12)) return hipErrorInvalidValue;
+  if (d.kind == 2 && d.c != (d.mixlo < 8 ? d.mixlo : 8)) return hipErrorInvalidValue;
   FwdArgs A{};
   A.d = d;
   A.S = S;
@@ -55,13 +73,12 @@ hipError_t launch_fwd13_ckpt_pass(const PassDesc& d, int nstates, int S, int p, 
   const dim3 grid((unsigned)total), blk(NT);
   {
     // the tile-independent tables of every state, then the pass
-    const hipError_t e = d.kind == 1
-        ? launch_pass_tables<G13, 1>(d, nstates, S, p, W, coef, fwd_tab_spec(d), tab, stream)
-        : launch_pass_tables<G13, 2>(d, nstates, S, p, W, coef, fwd_tab_spec(d), tab, stream);
+    const hipError_t e = g13_tables(d, nstates, S, p, W, coef, fwd_tab_spec(d), tab, stream);
     if (e != hipSuccess) return e;
   }
-#define DQ_K(K, M, T) \
-  hipLaunchKernelGGL((fwd_kernel<G13, K, M, T, true, true>), grid, blk, 0, stream, A)
+#define DQ_K(K, M, T)                                                                  \
+  hipLaunchKernelGGL((fwd_kernel<G13C<(K == 1 ? 4 : M < 8 ? M : 8)>, K, M, T, true, true>), \
+                     grid, blk, 0, stream, A)
   if (d.kind == 1) {
     if (pt == P_FIRST) DQ_K(1, 0, P_FIRST);
     else DQ_K(1, 0, P_MID);
@@ -88,6 +105,7 @@ hipError_t launch_bwd13_pass(const PassDesc& d, int shape, int nstates, int S, i
                              void* tab, hipStream_t stream) {
   if (d.n < 14 || d.n > 22 || p < 1 || p > 64 || nstates < 1 || S < 1) return hipErrorInvalidValue;
   if (d.kind == 1 ? d.mixlo != 0 : (d.mixlo < 4 || d.mixlo > 12)) return hipErrorInvalidValue;
+  if (d.kind == 2 && d.c != (d.mixlo < 8 ? d.mixlo : 8)) return hipErrorInvalidValue;
   const bool phase = d.ja <= d.jb;
   switch (shape) {
     case B_SEED:
@@ -124,13 +142,12 @@ hipError_t launch_bwd13_pass(const PassDesc& d, int shape, int nstates, int S, i
     // half-mixer at the phase layout flips bit 0, the middle shape undoes a phase
     const TabSpec ts{d.kind == 1 ? (shape == B_SEED ? d.lead : d.jb) : -1,
                      shape == B_MID ? d.jb : -1, -1.0};
-    const hipError_t e = d.kind == 1
-        ? launch_pass_tables<G13, 1>(d, nstates, S, p, W, coef, ts, tab, stream)
-        : launch_pass_tables<G13, 2>(d, nstates, S, p, W, coef, ts, tab, stream);
+    const hipError_t e = g13_tables(d, nstates, S, p, W, coef, ts, tab, stream);
     if (e != hipSuccess) return e;
   }
-#define DQ_B(K, M, T) \
-  hipLaunchKernelGGL((bwd_kernel<G13, K, M, T, true>), grid, blk, 0, stream, A)
+#define DQ_B(K, M, T)                                                                  \
+  hipLaunchKernelGGL((bwd_kernel<G13C<(K == 1 ? 4 : M < 8 ? M : 8)>, K, M, T, true>), grid, \
+                     blk, 0, stream, A)
 #define DQ_BT(K, M)                   \
   switch (shape) {                    \
     case B_SEED: DQ_B(K, M, B_SEED); break; \

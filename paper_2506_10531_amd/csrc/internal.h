@@ -87,7 +87,10 @@ bool make_plan_reg14(int n, int p, Plan* out);
 bool make_plan_reg13(int n, int p, Plan* out);
 // The same two-set plan for any tile size K and C low bits (K = 12, C = 2:
 // the complex128 gradient, 13 <= n <= 22).
-bool make_plan_reg2set(int n, int p, int K, int C, Plan* out);
+bool make_plan_reg2set(int n, int p, int K, int C, Plan* out, int cmax);
+inline bool make_plan_reg2set(int n, int p, int K, int C, Plan* out) {
+  return make_plan_reg2set(n, p, K, C, out, C);
+}
 
 // tab: TAB_BYTES of scratch per state for the pass's tile-independent tables
 // (computed by a small kernel launched first on the same stream).

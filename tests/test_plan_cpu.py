@@ -63,10 +63,10 @@ def test_plan_geometry_and_semantics(hctx, prec, n, p, grad):
         if reg14 or reg13 or reg13d or reg12:
             assert d["k"] == (14 if reg14 else 12 if reg12 else 13)
             assert d["kind"] == (1 if d["set"] == 0 else 2)
-            # complex64 forward: each kind-2 set has min(MIXLO, 8) contiguous
-            # low bits (its run of high bits holds exactly its qubits)
+            # complex64 forward and gradient: each kind-2 set has min(MIXLO, 8)
+            # contiguous low bits (its run of high bits holds exactly its qubits)
             assert d["c"] == (d["k"] if d["set"] == 0 else (2 if (reg13d or reg12) else
-                                                            4 if reg13 else min(d["mixlo"], 8)))
+                                                            min(d["mixlo"], 8)))
         tb = tile_bits(d, n)
         assert len(tb) == d["k"] and len(set(tb)) == d["k"]
         assert all(0 <= b < n for b in tb)
