@@ -192,10 +192,10 @@ struct BwdArgs {
   const LayerCoef* coef;
   double* part;  // [state][rec][2p + 2]
   int rec_base, nrec;
-  const void* tab = nullptr;  // per-state PassTab of the pass (PRE kernels)
+  const void* tab = nullptr;  // per-state PassTab of the pass (pass_tables_kernel)
 };
 
-template <class G, int KIND, int MIXLO, int BT, bool PRE = false>
+template <class G, int KIND, int MIXLO, int BT>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
 bwd_kernel(BwdArgs A) {
   using D = Dim<G>;
@@ -222,11 +222,11 @@ bwd_kernel(BwdArgs A) {
   V vp[NA], vl[NA];
   const V* const psi = reinterpret_cast<const V*>(A.psi);
   V* const lam = reinterpret_cast<V*>(A.lam);
-  // PRE: the tile-independent tables come from the state's PassTab
+  // the tile-independent tables come from the state's PassTab (A.tab)
   constexpr int NT1 = Tables<G::R>::N - Tables<G::R>::NF;
-  constexpr int NT2 = PRE && BT == B_MID ? (int)(sizeof(V) << G::R) / 8 : 0;
+  constexpr int NT2 = BT == B_MID ? (int)(sizeof(V) << G::R) / 8 : 0;
   const PassTab<G>* tab = reinterpret_cast<const PassTab<G>*>(A.tab) + st;
-  stage_context<PRE ? NT1 + NT2 : 0>(
+  stage_context<NT1 + NT2>(
       A.W + (size_t)(st / A.S) * n * n, n, A.coef + st * p, p, Wsh, cf, tid,
       [&] {
         load_tile<G, LA>(vp, psi + st * A.stride + zb, lane, wave, KIND, d.a);
@@ -245,12 +245,8 @@ bwd_kernel(BwdArgs A) {
   const bool f0 = KIND == 1 && L1.mode != 0;
   const double cblk = tile_context<K, G::C, KIND>(Wsh, n, d.a, zb, f0, fl, Wl, tmp, tid);
   const double gp_undo = BT == B_SEED ? 0.0 : -cf[d.jb].gp;
-  if (PRE) {
-    for (int e = tid; e < Tables<G::R>::NF; e += NT) table_entry<G, PL>(&T, fl, Wl, e);
-    lds_barrier();
-  } else {
-    tile_tables<G, PL>(&T, KF, fl, Wl, BT == B_MID, gp_undo, tid);
-  }
+  for (int e = tid; e < Tables<G::R>::NF; e += NT) table_entry<G, PL>(&T, fl, Wl, e);
+  lds_barrier();
   const int m = K - MIXLO;
   // Uniform scalars, all formed before the tiles are touched: q2 per qubit of
   // each undone half-mixer, the factor |.|^2 of the tan-form tiles at the

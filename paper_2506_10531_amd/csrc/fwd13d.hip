@@ -55,7 +55,7 @@ hipError_t launch_fwd13d_pass(const PassDesc& d, int nstates, int S, int p, cons
     if (e != hipSuccess) return e;
   }
 #define DQ_K(K, M, T) \
-  hipLaunchKernelGGL((fwd_kernel<G13D, K, M, T, false, true>), grid, blk, 0, stream, A)
+  hipLaunchKernelGGL((fwd_kernel<G13D, K, M, T>), grid, blk, 0, stream, A)
 #define DQ_PT(K, M)                           \
   switch (pt) {                               \
     case P_FIRST: DQ_K(K, M, P_FIRST); break; \

@@ -166,7 +166,7 @@ hipError_t launch_fwd14_pass(const PassDesc& d, int nstates, int S, int p,
     if (e != hipSuccess) return e;
   }
 #define DQ_K(K, M, T)                                                                        \
-  hipLaunchKernelGGL((fwd_kernel<G14T<(K == 1 ? 4 : M < 8 ? M : 8)>, K, M, T, false, true>), \
+  hipLaunchKernelGGL((fwd_kernel<G14T<(K == 1 ? 4 : M < 8 ? M : 8)>, K, M, T>),             \
                      grid, blk, 0, stream, A)
 #define DQ_PT(K, M)                           \
   switch (pt) {                               \

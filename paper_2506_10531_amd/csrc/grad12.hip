@@ -46,7 +46,7 @@ hipError_t launch_fwd12_ckpt_pass(const PassDesc& d, int nstates, int S, int p, 
     if (e != hipSuccess) return e;
   }
 #define DQ_K(K, M, T) \
-  hipLaunchKernelGGL((fwd_kernel<G12D, K, M, T, true, true>), grid, blk, 0, stream, A)
+  hipLaunchKernelGGL((fwd_kernel<G12D, K, M, T, true>), grid, blk, 0, stream, A)
   if (d.kind == 1) {
     if (pt == P_FIRST) DQ_K(1, 0, P_FIRST);
     else DQ_K(1, 0, P_MID);
@@ -116,7 +116,7 @@ hipError_t launch_bwd12_pass(const PassDesc& d, int shape, int nstates, int S, i
     if (e != hipSuccess) return e;
   }
 #define DQ_B(K, M, T) \
-  hipLaunchKernelGGL((bwd_kernel<G12D, K, M, T, true>), grid, blk, 0, stream, A)
+  hipLaunchKernelGGL((bwd_kernel<G12D, K, M, T>), grid, blk, 0, stream, A)
 #define DQ_BT(K, M)                   \
   switch (shape) {                    \
     case B_SEED: DQ_B(K, M, B_SEED); break; \

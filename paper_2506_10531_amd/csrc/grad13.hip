@@ -77,7 +77,7 @@ hipError_t launch_fwd13_ckpt_pass(const PassDesc& d, int nstates, int S, int p, 
     if (e != hipSuccess) return e;
   }
 #define DQ_K(K, M, T)                                                                  \
-  hipLaunchKernelGGL((fwd_kernel<G13C<(K == 1 ? 4 : M < 8 ? M : 8)>, K, M, T, true, true>), \
+  hipLaunchKernelGGL((fwd_kernel<G13C<(K == 1 ? 4 : M < 8 ? M : 8)>, K, M, T, true>),       \
                      grid, blk, 0, stream, A)
   if (d.kind == 1) {
     if (pt == P_FIRST) DQ_K(1, 0, P_FIRST);
@@ -146,7 +146,7 @@ hipError_t launch_bwd13_pass(const PassDesc& d, int shape, int nstates, int S, i
     if (e != hipSuccess) return e;
   }
 #define DQ_B(K, M, T)                                                                  \
-  hipLaunchKernelGGL((bwd_kernel<G13C<(K == 1 ? 4 : M < 8 ? M : 8)>, K, M, T, true>), grid, \
+  hipLaunchKernelGGL((bwd_kernel<G13C<(K == 1 ? 4 : M < 8 ? M : 8)>, K, M, T>), grid,       \
                      blk, 0, stream, A)
 #define DQ_BT(K, M)                   \
   switch (shape) {                    \

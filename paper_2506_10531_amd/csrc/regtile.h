@@ -648,17 +648,6 @@ __device__ __forceinline__ typename G::V reg_factor(const double* Wl, double gp,
   return unitv<typename G::V>(gp * k);
 }
 
-// Tables of layout PL and the per-tile factors KF[r] = e^{-i 2 pi gp K(r)}
-// (when gp is finite).  Ends with a barrier.
-template <class G, int PL>
-__device__ __forceinline__ void tile_tables(Tables<G::R>* T, typename G::V* KF, const double* fl,
-                                            const double* Wl, bool kf, double gp, int tid) {
-  constexpr int R = G::R, K = Dim<G>::K;
-#pragma unroll 1
-  for (int e = tid; e < Tables<R>::N; e += NT) table_entry<G, PL>(T, fl, Wl, e);
-  if (kf && tid < (1 << R)) KF[tid] = reg_factor<G, PL>(Wl, gp, tid);
-  lds_barrier();
-}
 
 // Stage the folded Q (n x n) and the state's layer coefficients in LDS while
 // the tile's loads are in flight: the Q reads are issued first, then issue(),
@@ -736,7 +725,7 @@ struct FwdArgs {
   const LayerCoef* coef;
   double* part;
   void* probs;      // |psi|^2 in the state precision
-  const void* tab = nullptr;  // per-state PassTab of the pass (PRE kernels)
+  const void* tab = nullptr;  // per-state PassTab of the pass (pass_tables_kernel)
 };
 
 // The tile-independent part of a pass's tables for one state: Tables
@@ -828,7 +817,7 @@ __device__ __forceinline__ uint64_t xcd_tile() {
 // pass shape keeps the tile's registers in place from load to store.  With
 // TRUE_OUT a stored state carries its pending mixer scalar (the adjoint
 // passes read such states).
-template <class G, int KIND, int MIXLO, int PT, bool TRUE_OUT = false, bool PRE = false>
+template <class G, int KIND, int MIXLO, int PT, bool TRUE_OUT = false>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
 fwd_kernel(FwdArgs A) {
   using D = Dim<G>;
@@ -854,12 +843,12 @@ fwd_kernel(FwdArgs A) {
   V* const gout = reinterpret_cast<V*>(A.out) + st * A.stride + zb;
   double* const Wsh = reinterpret_cast<double*>(buf);  // idle until the first transpose
   V v[NA];
-  // PRE: the tile-independent tables come from the state's PassTab, copied
-  // to LDS with the folded Q while the tile is in flight
+  // the tile-independent tables come from the state's PassTab (A.tab),
+  // copied to LDS with the folded Q while the tile is in flight
   constexpr int NT1 = Tables<G::R>::N - Tables<G::R>::NF;
-  constexpr int NT2 = PRE && PHASE ? (int)(sizeof(V) << G::R) / 8 : 0;
+  constexpr int NT2 = PHASE ? (int)(sizeof(V) << G::R) / 8 : 0;
   const PassTab<G>* tab = reinterpret_cast<const PassTab<G>*>(A.tab) + st;
-  stage_context<(PRE && PT != P_LEAD) ? NT1 + NT2 : 0>(
+  stage_context<PT != P_LEAD ? NT1 + NT2 : 0>(
       A.W + (size_t)(st / A.S) * n * n, n, A.coef + st * A.p, A.p, Wsh, cf, tid,
       [&] {
         if (PT != P_FIRST) load_tile<G, LA>(v, gin, lane, wave, KIND, d.a);
@@ -874,11 +863,9 @@ fwd_kernel(FwdArgs A) {
   // tile bit 0 flipped at PL (only when the pass mixes bit 0)
   const bool f0 = MIXLO == 0 && LEAD && cf[d.lead].mode != 0;
   const double cblk = tile_context<K, G::C, KIND>(Wsh, n, d.a, zb, f0, fl, Wl, tmp, tid);
-  if (PRE && PT != P_LEAD) {
+  if (PT != P_LEAD) {  // the tables' block-field entries
     for (int e = tid; e < Tables<G::R>::NF; e += NT) table_entry<G, PL>(&T, fl, Wl, e);
     lds_barrier();
-  } else if (PT != P_LEAD) {
-    tile_tables<G, PL>(&T, KF, fl, Wl, PHASE, PHASE ? cf[d.jb].gp : 0.0, tid);
   }
 
   // pending mixer scalar (at the phase, or at the outputs of the last pass)
