@@ -765,15 +765,20 @@ __device__ __forceinline__ double splitmix_u(uint64_t seed, uint64_t s) {
   return (double)(x >> 11) * 0x1.0p-53;
 }
 
-// One thread per (state, shot): locate u * total in the block CDF, then walk
-// the block in increasing z with an FP64 running sum.  C(z) from W in FP64.
+// One wave per (state, shot): locate u * total in the block CDF, then walk
+// the block in increasing z, 64 amplitudes per round (one coalesced load per
+// lane, an FP64 inclusive prefix over the wave on top of the running sum);
+// the first lane whose running sum exceeds the target gives z.  C(z) from W
+// in FP64, one row per lane.  Four shots per 256-thread work-group.
 template <typename T>
-__global__ void shots_kernel(int n, int shots, uint64_t seed, const uint64_t* seeds,
-                             const T* P, const double* bcdf, const double* W, int S,
-                             uint64_t* zout, double* czout) {
+__global__ void __launch_bounds__(256) shots_kernel(int n, int shots, uint64_t seed,
+                                                    const uint64_t* seeds, const T* P,
+                                                    const double* bcdf, const double* W,
+                                                    int S, uint64_t* zout, double* czout) {
   const int st = blockIdx.y;
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= shots) return;
+  const int lane = threadIdx.x & 63;
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (s >= shots) return;  // the whole wave
   const int bl = min(n, SBLK);
   const uint64_t nblk = 1ull << (n - bl);
   const double* cdf = bcdf + (uint64_t)st * nblk;
@@ -791,26 +796,36 @@ __global__ void shots_kernel(int n, int shots, uint64_t seed, const uint64_t* se
   }
   double run = lo ? cdf[lo - 1] : 0.0;
   const T* src = P + ((uint64_t)st << n) + (lo << bl);
-  uint64_t z = (lo << bl) + ((1ull << bl) - 1);
-  for (uint64_t i = 0; i < (1ull << bl); ++i) {
-    run += (double)src[i];
-    if (run > target) {
-      z = (lo << bl) + i;
+  const int len = 1 << bl;
+  uint64_t z = (lo << bl) + (uint64_t)(len - 1);  // rounding fallback: last of the block
+  for (int r = 0; r < len; r += 64) {
+    const int cnt = len - r < 64 ? len - r : 64;
+    double x = lane < cnt ? (double)src[r + lane] : 0.0;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const double y = __shfl_up(x, d);
+      if (lane >= d) x += y;
+    }
+    const uint64_t hit = __ballot(lane < cnt && run + x > target);
+    if (hit) {
+      z = (lo << bl) + (uint64_t)(r + __ffsll((unsigned long long)hit) - 1);
       break;
     }
+    run += __shfl(x, 63);
   }
   const double* Wb = W + (size_t)(st / S) * n * n;
   double c = 0.0;
-  for (int i = 0; i < n; ++i) {
-    if ((z >> i) & 1ull) {
-      double r = Wb[i * n + i];
-      for (int j = 0; j < i; ++j)
-        if ((z >> j) & 1ull) r += Wb[i * n + j];
-      c += r;
-    }
+  if (lane < n && ((z >> lane) & 1ull)) {
+    c = Wb[lane * n + lane];
+    for (int j = 0; j < lane; ++j)
+      if ((z >> j) & 1ull) c += Wb[lane * n + j];
   }
-  zout[(uint64_t)st * shots + s] = z;
-  czout[(uint64_t)st * shots + s] = c;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d);
+  if (lane == 0) {
+    zout[(uint64_t)st * shots + s] = z;
+    czout[(uint64_t)st * shots + s] = c;
+  }
 }
 
 __global__ void best_kernel(int shots, const uint64_t* z, const double* cz,
@@ -1038,13 +1053,13 @@ hipError_t launch_sample(int prec, int n, int nstates, const void* probs,
                        dim3(nt), 0, stream, n, (const float*)probs, bsum);
   hipLaunchKernelGGL(block_scan_kernel, dim3(nstates), dim3(1024), 0, stream, n,
                      bsum, bcdf);
-  const int sb = (shots + 63) / 64;
+  const int sb = (shots + 3) / 4;
   if (prec == 0)
-    hipLaunchKernelGGL(shots_kernel<double>, dim3(sb, nstates), dim3(64), 0,
+    hipLaunchKernelGGL(shots_kernel<double>, dim3(sb, nstates), dim3(256), 0,
                        stream, n, shots, seed, seeds, (const double*)probs, bcdf, W,
                        S, z, cz);
   else
-    hipLaunchKernelGGL(shots_kernel<float>, dim3(sb, nstates), dim3(64), 0,
+    hipLaunchKernelGGL(shots_kernel<float>, dim3(sb, nstates), dim3(256), 0,
                        stream, n, shots, seed, seeds, (const float*)probs, bcdf, W,
                        S, z, cz);
   hipLaunchKernelGGL(best_kernel, dim3(nstates), dim3(256), 0, stream, shots, z,
