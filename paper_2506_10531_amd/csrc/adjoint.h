@@ -192,7 +192,7 @@ struct BwdArgs {
   const LayerCoef* coef;
   double* part;  // [state][rec][2p + 2]
   int rec_base, nrec;
-  const void* tab = nullptr;  // per-state PassTab of the pass (pass_tables_kernel)
+  const void* tab = nullptr;  // the pass's PassTab records, TAB_BYTES apart (all_tables_kernel)
 };
 
 template <class G, int KIND, int MIXLO, int BT>
@@ -225,7 +225,8 @@ bwd_kernel(BwdArgs A) {
   // the tile-independent tables come from the state's PassTab (A.tab)
   constexpr int NT1 = Tables<G::R>::N - Tables<G::R>::NF;
   constexpr int NT2 = BT == B_MID ? (int)(sizeof(V) << G::R) / 8 : 0;
-  const PassTab<G>* tab = reinterpret_cast<const PassTab<G>*>(A.tab) + st;
+  const PassTab<G>* tab =
+      reinterpret_cast<const PassTab<G>*>(static_cast<const char*>(A.tab) + st * TAB_BYTES);
   stage_context<NT1 + NT2>(
       A.W + (size_t)(st / A.S) * n * n, n, A.coef + st * p, p, Wsh, cf, tid,
       [&] {

@@ -369,7 +369,10 @@ int make_layout(int op, int prec, int B, int n, int p, int S, int shots,
   const Plan& P = L->plan;
   L->iW = L->cv.add((size_t)B * n * n * sizeof(double));
   L->iC = L->cv.add(L->nstates * p * sizeof(LayerCoef));
-  L->iTab = L->cv.add(L->nstates * TAB_BYTES);
+  // per-state tables of every register-tile pass (one record per pass and
+  // state; the gradient's checkpoint and adjoint passes have their own)
+  const size_t ntab = P.pass[0].kind == 0 ? 1 : (grad ? 2 * (size_t)P.npass - 1 : P.npass);
+  L->iTab = L->cv.add(L->nstates * TAB_BYTES * ntab);
   if (!grad) {
     const PassDesc& last = P.pass[P.npass - 1];
     L->iPart = L->cv.add(L->nstates * ntiles(last) * 2 * sizeof(double));
@@ -421,6 +424,9 @@ int run_forward(const Layout& L, char* base, const double* Q,
   if (e != hipSuccess) return hip_error(e, "prep");
   const uint64_t stride = 1ull << L.n;
   const double sb = (double)L.state_bytes * L.nstates;
+  char* const tabs = L.at(base, L.iTab);
+  const size_t tstride = L.nstates * TAB_BYTES;
+  const bool reg = L.plan.pass[0].kind != 0;
   for (int i = 0; i < L.plan.npass; ++i) {
     PassDesc d = L.plan.pass[i];
     const bool last = i == L.plan.npass - 1;
@@ -431,14 +437,27 @@ int run_forward(const Layout& L, char* base, const double* Q,
     if (d.flags & F_WRITE) bytes += sb;
     if (d.flags & F_PROBS) bytes += sb / 2;
     TimerScope ts(tm, s, bytes);
+    if (reg && i == 0) {
+      // every pass's tables in one launch, inside the first pass's bracket
+      TabJobs J{};
+      J.njobs = L.plan.npass;
+      for (int k = 0; k < L.plan.npass; ++k) {
+        const PassDesc& dk = L.plan.pass[k];
+        J.job[k] = tab_job(dk, fwd_tab_spec(dk), dk.ja <= dk.jb || (dk.flags & F_REDUCE));
+      }
+      e = L.prec == QAOA_C64
+              ? launch_fwd14_tables(J, L.n, (int)L.nstates, L.S, L.p, W, coef, tabs, s)
+              : launch_fwd13d_tables(J, L.n, (int)L.nstates, L.S, L.p, W, coef, tabs, s);
+      if (e != hipSuccess) return hip_error(e, "pass tables");
+    }
     if (d.kind && L.prec == QAOA_C64)
       e = launch_fwd14_pass(d, (int)L.nstates, L.S, L.p, state,
                             (last && psi) ? psi : state, stride, W, coef, part, probs,
-                            L.at(base, L.iTab), s);
+                            tabs + i * tstride, s);
     else if (d.kind)
       e = launch_fwd13d_pass(d, (int)L.nstates, L.S, L.p, state,
                              (last && psi) ? psi : state, stride, W, coef, part, probs,
-                             L.at(base, L.iTab), s);
+                             tabs + i * tstride, s);
     else
       e = launch_fwd_pass(L.prec, d, (int)L.nstates, L.S, L.p, state,
                           (last && psi) ? psi : state, stride, W, coef, part, probs, s);
@@ -500,27 +519,47 @@ int enqueue_grad(const Layout& L, char* base, const double* Q,
   const uint64_t stride = 1ull << L.n;
   const double sb = (double)L.state_bytes * L.nstates;
   auto ck = [&](int i) { return (void*)L.at(base, L.iCk[i]); };
-  void* const tab = L.at(base, L.iTab);
+  char* const tabs = L.at(base, L.iTab);
+  const size_t tstride = (size_t)ns * TAB_BYTES;
   void* lam = np > 1 ? (void*)L.at(base, L.iLam) : nullptr;
   if ((P.K == 13 || P.K == 12) && P.pass[0].kind != 0) {
     const bool c128 = P.K == 12;
     // register-tile gradient: checkpoint passes, the seed pass, middle
     // adjoint passes, and the first pass's adjoint
+    // every pass's tables in one launch: checkpoint pass i at job i, the
+    // adjoint of pass i at job np - 1 + i (its undone half-mixer flips bit 0
+    // and the middle shape undoes a phase)
+    auto shape_of = [&](int i) { return i == np - 1 ? 0 : (i == 0 ? 2 : 1); };
+    {
+      TabJobs J{};
+      J.njobs = 2 * np - 1;
+      for (int i = 0; i + 1 < np; ++i) J.job[i] = tab_job(P.pass[i], fwd_tab_spec(P.pass[i]), true);
+      for (int i = 0; i < np; ++i) {
+        const PassDesc& d = P.pass[i];
+        const int sh = shape_of(i);
+        const TabSpec t{d.kind == 1 ? (sh == 0 ? d.lead : d.jb) : -1, sh == 1 ? d.jb : -1, -1.0};
+        J.job[np - 1 + i] = tab_job(d, t, true);
+      }
+      TimerScope ts(tm, s, 0.0);
+      e = c128 ? launch_grad12_tables(J, L.n, ns, S, p, W, coef, tabs, s)
+               : launch_grad13_tables(J, L.n, ns, S, p, W, coef, tabs, s);
+      if (e != hipSuccess) return hip_error(e, "pass tables");
+    }
     for (int i = 0; i + 1 < np; ++i) {
       PassDesc d = P.pass[i];
       TimerScope ts(tm, s, (i == 0 ? 0.0 : sb) + sb);
       e = c128 ? launch_fwd12_ckpt_pass(d, ns, S, p, i ? ck(i - 1) : nullptr, ck(i), stride, W,
-                                        coef, tab, s)
+                                        coef, tabs + i * tstride, s)
                : launch_fwd13_ckpt_pass(d, ns, S, p, i ? ck(i - 1) : nullptr, ck(i), stride, W,
-                                        coef, tab, s);
+                                        coef, tabs + i * tstride, s);
       if (e != hipSuccess) return hip_error(e, "checkpoint pass");
     }
     for (int i = np - 1; i >= 0; --i) {
-      const int shape = i == np - 1 ? 0 : (i == 0 ? 2 : 1);
+      const int shape = shape_of(i);
       TimerScope ts(tm, s, (shape == 1 ? 3 : 2) * sb);
       e = (c128 ? launch_bwd12_pass : launch_bwd13_pass)(
           P.pass[i], shape, ns, S, p, ck(i == np - 1 ? i - 1 : i), lam, stride, W, coef, part,
-          L.rec_base[i], L.nrec, tab, s);
+          L.rec_base[i], L.nrec, tabs + (np - 1 + i) * tstride, s);
       if (e != hipSuccess) return hip_error(e, "adjoint pass");
     }
     double* outs[3] = {dgamma, dbeta, expect};

@@ -47,13 +47,7 @@ hipError_t launch_fwd13d_pass(const PassDesc& d, int nstates, int S, int p, cons
   const uint64_t total = (uint64_t)nstates << (d.n - 13);
   if (total > 0xFFFFFFFFull) return hipErrorInvalidValue;
   const dim3 grid((unsigned)total), blk(NT);
-  if (pt != P_LEAD) {
-    // the tile-independent tables of every state, then the pass
-    const hipError_t e = d.kind == 1
-        ? launch_pass_tables<G13D, 1>(d, nstates, S, p, W, coef, fwd_tab_spec(d), tab, stream)
-        : launch_pass_tables<G13D, 2>(d, nstates, S, p, W, coef, fwd_tab_spec(d), tab, stream);
-    if (e != hipSuccess) return e;
-  }
+  if (pt != P_LEAD && !tab) return hipErrorInvalidValue;
 #define DQ_K(K, M, T) \
   hipLaunchKernelGGL((fwd_kernel<G13D, K, M, T>), grid, blk, 0, stream, A)
 #define DQ_PT(K, M)                           \
@@ -87,6 +81,12 @@ hipError_t launch_fwd13d_pass(const PassDesc& d, int nstates, int S, int p, cons
 #undef DQ_PT
 #undef DQ_K
   return hipGetLastError();
+}
+
+hipError_t launch_fwd13d_tables(const TabJobs& J, int n, int nstates, int S, int p,
+                                const double* W, const LayerCoef* coef, void* tab,
+                                hipStream_t stream) {
+  return launch_all_tables<G13D>(J, n, nstates, S, p, W, coef, tab, stream);
 }
 
 }  // namespace dq

@@ -152,19 +152,7 @@ hipError_t launch_fwd14_pass(const PassDesc& d, int nstates, int S, int p,
   const uint64_t total = (uint64_t)nstates << (d.n - 14);
   if (total > 0xFFFFFFFFull) return hipErrorInvalidValue;
   const dim3 grid((unsigned)total), blk(NT);
-  if (pt != P_LEAD) {
-    // the tile-independent tables of every state, then the pass
-    const TabSpec ts = fwd_tab_spec(d);
-#define DQ_T(KK, CC) launch_pass_tables<G14T<CC>, KK>(d, nstates, S, p, W, coef, ts, tab, stream)
-    const hipError_t e = d.kind == 1 ? DQ_T(1, 4)
-                         : d.c == 4  ? DQ_T(2, 4)
-                         : d.c == 5  ? DQ_T(2, 5)
-                         : d.c == 6  ? DQ_T(2, 6)
-                         : d.c == 7  ? DQ_T(2, 7)
-                                     : DQ_T(2, 8);
-#undef DQ_T
-    if (e != hipSuccess) return e;
-  }
+  if (pt != P_LEAD && !tab) return hipErrorInvalidValue;
 #define DQ_K(K, M, T)                                                                        \
   hipLaunchKernelGGL((fwd_kernel<G14T<(K == 1 ? 4 : M < 8 ? M : 8)>, K, M, T>),             \
                      grid, blk, 0, stream, A)
@@ -198,6 +186,12 @@ hipError_t launch_fwd14_pass(const PassDesc& d, int nstates, int S, int p,
 #undef DQ_PT
 #undef DQ_K
   return hipGetLastError();
+}
+
+hipError_t launch_fwd14_tables(const TabJobs& J, int n, int nstates, int S, int p,
+                               const double* W, const LayerCoef* coef, void* tab,
+                               hipStream_t stream) {
+  return launch_all_tables<G14T<4>>(J, n, nstates, S, p, W, coef, tab, stream);
 }
 
 }  // namespace dq

@@ -38,13 +38,7 @@ hipError_t launch_fwd12_ckpt_pass(const PassDesc& d, int nstates, int S, int p, 
   const uint64_t total = (uint64_t)nstates << (d.n - 12);
   if (total > 0xFFFFFFFFull) return hipErrorInvalidValue;
   const dim3 grid((unsigned)total), blk(NT);
-  {
-    // the tile-independent tables of every state, then the pass
-    const hipError_t e = d.kind == 1
-        ? launch_pass_tables<G12D, 1>(d, nstates, S, p, W, coef, fwd_tab_spec(d), tab, stream)
-        : launch_pass_tables<G12D, 2>(d, nstates, S, p, W, coef, fwd_tab_spec(d), tab, stream);
-    if (e != hipSuccess) return e;
-  }
+  if (!tab) return hipErrorInvalidValue;
 #define DQ_K(K, M, T) \
   hipLaunchKernelGGL((fwd_kernel<G12D, K, M, T, true>), grid, blk, 0, stream, A)
   if (d.kind == 1) {
@@ -105,16 +99,7 @@ hipError_t launch_bwd12_pass(const PassDesc& d, int shape, int nstates, int S, i
   const uint64_t total = (uint64_t)nstates << (d.n - 12);
   if (total > 0xFFFFFFFFull) return hipErrorInvalidValue;
   const dim3 grid((unsigned)total), blk(NT);
-  {
-    // the tile-independent tables of every state, then the pass: the undone
-    // half-mixer at the phase layout flips bit 0, the middle shape undoes a phase
-    const TabSpec ts{d.kind == 1 ? (shape == B_SEED ? d.lead : d.jb) : -1,
-                     shape == B_MID ? d.jb : -1, -1.0};
-    const hipError_t e = d.kind == 1
-        ? launch_pass_tables<G12D, 1>(d, nstates, S, p, W, coef, ts, tab, stream)
-        : launch_pass_tables<G12D, 2>(d, nstates, S, p, W, coef, ts, tab, stream);
-    if (e != hipSuccess) return e;
-  }
+  if (!tab) return hipErrorInvalidValue;
 #define DQ_B(K, M, T) \
   hipLaunchKernelGGL((bwd_kernel<G12D, K, M, T>), grid, blk, 0, stream, A)
 #define DQ_BT(K, M)                   \
@@ -145,6 +130,12 @@ hipError_t launch_bwd12_pass(const PassDesc& d, int shape, int nstates, int S, i
 #undef DQ_BT
 #undef DQ_B
   return hipGetLastError();
+}
+
+hipError_t launch_grad12_tables(const TabJobs& J, int n, int nstates, int S, int p,
+                                const double* W, const LayerCoef* coef, void* tab,
+                                hipStream_t stream) {
+  return launch_all_tables<G12D>(J, n, nstates, S, p, W, coef, tab, stream);
 }
 
 }  // namespace dq

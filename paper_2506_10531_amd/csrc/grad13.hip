@@ -34,18 +34,6 @@ template <int C>
 using G13C = G13T<float2, float, C>;
 using G13 = G13C<4>;
 
-// The pass tables for kind KK (kind-2 geometry by the pass's C).
-inline hipError_t g13_tables(const PassDesc& d, int nstates, int S, int p, const double* W,
-                             const LayerCoef* coef, TabSpec ts, void* tab, hipStream_t stream) {
-#define DQ_T(KK, CC) launch_pass_tables<G13C<CC>, KK>(d, nstates, S, p, W, coef, ts, tab, stream)
-  return d.kind == 1 ? DQ_T(1, 4)
-         : d.c == 4  ? DQ_T(2, 4)
-         : d.c == 5  ? DQ_T(2, 5)
-         : d.c == 6  ? DQ_T(2, 6)
-         : d.c == 7  ? DQ_T(2, 7)
-                     : DQ_T(2, 8);
-#undef DQ_T
-}
 
 }  // namespace
 
@@ -71,11 +59,7 @@ hipError_t launch_fwd13_ckpt_pass(const PassDesc& d, int nstates, int S, int p, 
   const uint64_t total = (uint64_t)nstates << (d.n - 13);
   if (total > 0xFFFFFFFFull) return hipErrorInvalidValue;
   const dim3 grid((unsigned)total), blk(NT);
-  {
-    // the tile-independent tables of every state, then the pass
-    const hipError_t e = g13_tables(d, nstates, S, p, W, coef, fwd_tab_spec(d), tab, stream);
-    if (e != hipSuccess) return e;
-  }
+  if (!tab) return hipErrorInvalidValue;
 #define DQ_K(K, M, T)                                                                  \
   hipLaunchKernelGGL((fwd_kernel<G13C<(K == 1 ? 4 : M < 8 ? M : 8)>, K, M, T, true>),       \
                      grid, blk, 0, stream, A)
@@ -137,14 +121,7 @@ hipError_t launch_bwd13_pass(const PassDesc& d, int shape, int nstates, int S, i
   const uint64_t total = (uint64_t)nstates << (d.n - 13);
   if (total > 0xFFFFFFFFull) return hipErrorInvalidValue;
   const dim3 grid((unsigned)total), blk(NT);
-  {
-    // the tile-independent tables of every state, then the pass: the undone
-    // half-mixer at the phase layout flips bit 0, the middle shape undoes a phase
-    const TabSpec ts{d.kind == 1 ? (shape == B_SEED ? d.lead : d.jb) : -1,
-                     shape == B_MID ? d.jb : -1, -1.0};
-    const hipError_t e = g13_tables(d, nstates, S, p, W, coef, ts, tab, stream);
-    if (e != hipSuccess) return e;
-  }
+  if (!tab) return hipErrorInvalidValue;
 #define DQ_B(K, M, T)                                                                  \
   hipLaunchKernelGGL((bwd_kernel<G13C<(K == 1 ? 4 : M < 8 ? M : 8)>, K, M, T>), grid,       \
                      blk, 0, stream, A)
@@ -175,6 +152,12 @@ hipError_t launch_bwd13_pass(const PassDesc& d, int shape, int nstates, int S, i
 #undef DQ_BT
 #undef DQ_B
   return hipGetLastError();
+}
+
+hipError_t launch_grad13_tables(const TabJobs& J, int n, int nstates, int S, int p,
+                                const double* W, const LayerCoef* coef, void* tab,
+                                hipStream_t stream) {
+  return launch_all_tables<G13C<4>>(J, n, nstates, S, p, W, coef, tab, stream);
 }
 
 }  // namespace dq

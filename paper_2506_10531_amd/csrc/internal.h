@@ -92,13 +92,66 @@ inline bool make_plan_reg2set(int n, int p, int K, int C, Plan* out) {
   return make_plan_reg2set(n, p, K, C, out, C);
 }
 
-// tab: TAB_BYTES of scratch per state for the pass's tile-independent tables
-// (computed by a small kernel launched first on the same stream).
+// tab: the pass's tile-independent tables, one record of TAB_BYTES per state
+// (written by launch_*_tables before the passes).
 hipError_t launch_fwd14_pass(const PassDesc& d, int nstates, int S, int p,
                              const void* in, void* out, uint64_t state_stride,
                              const double* W, const LayerCoef* coef,
                              double* part, void* probs, void* tab, hipStream_t stream);
 constexpr size_t TAB_BYTES = 8192;
+
+// Which layer coefficients a pass's tables use: the cot form of layer
+// flip_layer flips tile bit 0 (set 0 only; -1: no flip), and the register
+// factors are e^{-i 2 pi kf_sign gp K(r)} with gp of layer kf_layer (-1: none).
+struct TabSpec {
+  int flip_layer;
+  int kf_layer;
+  double kf_sign;
+};
+
+// The forward pass's spec: its lead flips bit 0, its phase layer gives KF.
+inline TabSpec fwd_tab_spec(const PassDesc& d) {
+  return TabSpec{d.kind == 1 && d.lead >= 0 ? d.lead : -1, d.ja <= d.jb ? d.jb : -1, 1.0};
+}
+
+// The tables of one pass, as a job of all_tables_kernel: the pass's tile
+// geometry (kind; contiguous low tile bits c and run start a for kind 2) and
+// its TabSpec.  kind 0: the pass needs no tables (lead-only passes).
+struct TabJob {
+  int8_t kind, c, a, flip, kfl, neg;
+  int8_t pad[2];
+};
+constexpr int MAX_TAB_JOBS = 200;
+struct TabJobs {
+  int njobs;
+  TabJob job[MAX_TAB_JOBS];
+};
+inline TabJob tab_job(const PassDesc& d, const TabSpec& t, bool needed) {
+  TabJob j{};
+  j.kind = (int8_t)(needed ? d.kind : 0);
+  j.c = (int8_t)d.c;
+  j.a = (int8_t)d.a;
+  j.flip = (int8_t)t.flip_layer;
+  j.kfl = (int8_t)t.kf_layer;
+  j.neg = (int8_t)(t.kf_sign < 0.0);
+  return j;
+}
+
+// One launch computing every pass's tables of a call (all_tables_kernel), per
+// geometry family; tab: J.njobs * nstates records of TAB_BYTES, pass j's at
+// tab + j * nstates * TAB_BYTES.
+hipError_t launch_fwd14_tables(const TabJobs& J, int n, int nstates, int S, int p,
+                               const double* W, const LayerCoef* coef, void* tab,
+                               hipStream_t stream);
+hipError_t launch_fwd13d_tables(const TabJobs& J, int n, int nstates, int S, int p,
+                                const double* W, const LayerCoef* coef, void* tab,
+                                hipStream_t stream);
+hipError_t launch_grad13_tables(const TabJobs& J, int n, int nstates, int S, int p,
+                                const double* W, const LayerCoef* coef, void* tab,
+                                hipStream_t stream);
+hipError_t launch_grad12_tables(const TabJobs& J, int n, int nstates, int S, int p,
+                                const double* W, const LayerCoef* coef, void* tab,
+                                hipStream_t stream);
 // complex128 register-tile pass on 13-qubit tiles (kind-2 sets with C = 2).
 hipError_t launch_fwd13d_pass(const PassDesc& d, int nstates, int S, int p,
                               const void* in, void* out, uint64_t state_stride,

@@ -725,7 +725,7 @@ struct FwdArgs {
   const LayerCoef* coef;
   double* part;
   void* probs;      // |psi|^2 in the state precision
-  const void* tab = nullptr;  // per-state PassTab of the pass (pass_tables_kernel)
+  const void* tab = nullptr;  // the pass's PassTab records, TAB_BYTES apart (all_tables_kernel)
 };
 
 // The tile-independent part of a pass's tables for one state: Tables
@@ -736,55 +736,69 @@ struct PassTab {
   typename G::V KF[1 << G::R];
 };
 
-// Which layer coefficients a pass's tables use: the cot form of layer
-// flip_layer flips tile bit 0 (set 0 only; -1: no flip), and the register
-// factors are e^{-i 2 pi kf_sign gp K(r)} with gp of layer kf_layer (-1: none).
-struct TabSpec {
-  int flip_layer;
-  int kf_layer;
-  double kf_sign;
-};
 
-// One work-group per state: the PassTab of pass d (kind KIND) for state
-// blockIdx.x, from the folded Q and the state's layer coefficients.
-template <class G, int KIND>
-__global__ void __launch_bounds__(NT) pass_tables_kernel(PassDesc d, int S, int p,
-                                                         const double* W, const LayerCoef* coef,
-                                                         TabSpec spec, PassTab<G>* out) {
-  constexpr int K = Dim<G>::K, R = G::R, PL = G::template PL<KIND>;
+// Couplings among the tile bits for a run-time kind and c (the job's).
+template <int K>
+__device__ __forceinline__ void tile_couplings_rt(const double* Wsh, int n, int kind, int c,
+                                                  int a, bool f0, double* Wl, int tid) {
+  for (int e = tid; e < K * K; e += NT) {
+    const int i = e / K, j = e - K * i;
+    const int pi = (kind == 1 || i < c) ? i : a + i - c;
+    const int pj = (kind == 1 || j < c) ? j : a + j - c;
+    const double w = (i == j) ? 0.0 : Wsh[pi * n + pj];
+    Wl[e] = (f0 && (i == 0) != (j == 0)) ? -w : w;
+  }
+}
+
+template <class G, int PL>
+__device__ __forceinline__ void tab_entries(PassTab<G>* o, const double* Wl, int kfl, double gp,
+                                            int tid) {
+  constexpr int R = G::R;
+  for (int e = Tables<R>::NF + tid; e < Tables<R>::N; e += NT) table_entry<G, PL>(&o->T, nullptr, Wl, e);
+  if (kfl >= 0 && tid < (1 << R)) o->KF[tid] = reg_factor<G, PL>(Wl, gp, tid);
+}
+
+// All tables of a call in one launch: work-group (state blockIdx.x, job
+// blockIdx.y) writes the PassTab of that pass and state at record
+// job * nstates + state (TAB_BYTES apart).  G stands for its geometry family:
+// the layouts do not depend on the number of contiguous low bits.
+template <class G>
+__global__ void __launch_bounds__(NT) all_tables_kernel(TabJobs J, int n, int S, int p,
+                                                        int nstates, const double* W,
+                                                        const LayerCoef* coef, char* out) {
+  constexpr int K = Dim<G>::K;
+  const TabJob jb = J.job[blockIdx.y];
+  if (jb.kind == 0) return;
   __shared__ double Wsh[34 * 34];
   __shared__ double Wl[K * K];
   __shared__ LayerCoef cf[64];
-  const int tid = threadIdx.x, n = d.n, st = blockIdx.x;
+  const int tid = threadIdx.x, st = blockIdx.x;
   const double* Ws = W + (size_t)(st / S) * n * n;
   for (int e = tid; e < n * n; e += NT) Wsh[e] = Ws[e];
   if (tid < p) cf[tid] = coef[(size_t)st * p + tid];
   lds_barrier();
-  const bool f0 = KIND == 1 && spec.flip_layer >= 0 && cf[spec.flip_layer].mode != 0;
-  tile_couplings<K, G::C, KIND>(Wsh, n, d.a, f0, Wl, tid);
+  const bool f0 = jb.kind == 1 && jb.flip >= 0 && cf[jb.flip].mode != 0;
+  tile_couplings_rt<K>(Wsh, n, jb.kind, jb.c, jb.a, f0, Wl, tid);
   lds_barrier();
-  PassTab<G>* o = out + st;
-  for (int e = Tables<R>::NF + tid; e < Tables<R>::N; e += NT) table_entry<G, PL>(&o->T, nullptr, Wl, e);
-  if (spec.kf_layer >= 0 && tid < (1 << R))
-    o->KF[tid] = reg_factor<G, PL>(Wl, spec.kf_sign * cf[spec.kf_layer].gp, tid);
+  PassTab<G>* o =
+      reinterpret_cast<PassTab<G>*>(out + ((size_t)blockIdx.y * nstates + st) * TAB_BYTES);
+  const double gp = jb.kfl >= 0 ? (jb.neg ? -cf[jb.kfl].gp : cf[jb.kfl].gp) : 0.0;
+  if (jb.kind == 1) tab_entries<G, G::template PL<1>>(o, Wl, jb.kfl, gp, tid);
+  else tab_entries<G, G::template PL<2>>(o, Wl, jb.kfl, gp, tid);
 }
 
-// Queue pass_tables_kernel for nstates states (tab: nstates records).
-template <class G, int KIND>
-inline hipError_t launch_pass_tables(const PassDesc& d, int nstates, int S, int p,
-                                     const double* W, const LayerCoef* coef, TabSpec spec,
-                                     void* tab, hipStream_t stream) {
+template <class G>
+inline hipError_t launch_all_tables(const TabJobs& J, int n, int nstates, int S, int p,
+                                    const double* W, const LayerCoef* coef, void* tab,
+                                    hipStream_t stream) {
   static_assert(sizeof(PassTab<G>) <= TAB_BYTES, "pass tables exceed their scratch");
-  if (!tab || nstates < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((pass_tables_kernel<G, KIND>), dim3(nstates), dim3(NT), 0, stream, d, S, p,
-                     W, coef, spec, reinterpret_cast<PassTab<G>*>(tab));
+  if (!tab || nstates < 1 || J.njobs < 1 || J.njobs > MAX_TAB_JOBS)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(all_tables_kernel<G>, dim3(nstates, J.njobs), dim3(NT), 0, stream, J, n, S,
+                     p, nstates, W, coef, static_cast<char*>(tab));
   return hipGetLastError();
 }
 
-// The forward pass's spec: its lead flips bit 0, its phase layer gives KF.
-inline TabSpec fwd_tab_spec(const PassDesc& d) {
-  return TabSpec{d.kind == 1 && d.lead >= 0 ? d.lead : -1, d.ja <= d.jb ? d.jb : -1, 1.0};
-}
 
 // Pass shape of a descriptor, or -1.
 inline int pass_shape(const PassDesc& d, int p) {
@@ -847,7 +861,8 @@ fwd_kernel(FwdArgs A) {
   // copied to LDS with the folded Q while the tile is in flight
   constexpr int NT1 = Tables<G::R>::N - Tables<G::R>::NF;
   constexpr int NT2 = PHASE ? (int)(sizeof(V) << G::R) / 8 : 0;
-  const PassTab<G>* tab = reinterpret_cast<const PassTab<G>*>(A.tab) + st;
+  const PassTab<G>* tab =
+      reinterpret_cast<const PassTab<G>*>(static_cast<const char*>(A.tab) + st * TAB_BYTES);
   stage_context<PT != P_LEAD ? NT1 + NT2 : 0>(
       A.W + (size_t)(st / A.S) * n * n, n, A.coef + st * A.p, A.p, Wsh, cf, tid,
       [&] {
