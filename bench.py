@@ -435,7 +435,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1); multi-GPU "
+        print("bench.py: runs on one GPU only (--gpus 1); multi-GPU "
               "runs are not supported", file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
