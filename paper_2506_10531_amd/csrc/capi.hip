@@ -18,6 +18,9 @@
 
 namespace dq {
 
+static_assert(MAX_TAB_JOBS >= 2 * (2 * QAOA_MAX_P + 1) - 1,
+              "a two-set register-tile gradient at QAOA_MAX_P layers fits the table jobs");
+
 // ---- errors -------------------------------------------------------------------
 
 static thread_local std::string g_err;
@@ -440,6 +443,9 @@ int run_forward(const Layout& L, char* base, const double* Q,
     if (reg && i == 0) {
       // every pass's tables in one launch, inside the first pass's bracket
       TabJobs J{};
+      if (L.plan.npass > MAX_TAB_JOBS)
+        return set_error(QAOA_ERR_INVALID_ARG, "%d passes exceed the %d table jobs of a call",
+                         L.plan.npass, MAX_TAB_JOBS);
       J.njobs = L.plan.npass;
       for (int k = 0; k < L.plan.npass; ++k) {
         const PassDesc& dk = L.plan.pass[k];
@@ -532,6 +538,9 @@ int enqueue_grad(const Layout& L, char* base, const double* Q,
     auto shape_of = [&](int i) { return i == np - 1 ? 0 : (i == 0 ? 2 : 1); };
     {
       TabJobs J{};
+      if (2 * np - 1 > MAX_TAB_JOBS)
+        return set_error(QAOA_ERR_INVALID_ARG, "%d passes exceed the %d table jobs of a call",
+                         np, MAX_TAB_JOBS);
       J.njobs = 2 * np - 1;
       for (int i = 0; i + 1 < np; ++i) J.job[i] = tab_job(P.pass[i], fwd_tab_spec(P.pass[i]), true);
       for (int i = 0; i < np; ++i) {

@@ -121,7 +121,11 @@ struct TabJob {
   int8_t kind, c, a, flip, kfl, neg;
   int8_t pad[2];
 };
-constexpr int MAX_TAB_JOBS = 200;
+// The most table jobs of one call: a register-tile gradient on two qubit
+// sets at 64 layers has 2p + 1 passes, each with a checkpoint and an adjoint
+// job but the last, i.e. 2 (2p + 1) - 1 = 257.  The list travels as a kernel
+// argument (8 bytes a job).
+constexpr int MAX_TAB_JOBS = 257;
 struct TabJobs {
   int njobs;
   TabJob job[MAX_TAB_JOBS];

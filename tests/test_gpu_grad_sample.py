@@ -59,6 +59,24 @@ def test_grad_matches_oracle(api, prec, n, p):
         assert np.max(np.abs(e[bi] - eo)) <= etol
 
 
+@pytest.mark.parametrize("prec,n", [("c64", 14), ("c128", 13)])
+def test_grad_at_max_layers(api, prec, n):
+    """QAOA_MAX_P = 64 layers on register tiles: 2p + 1 = 129 passes, whose
+    checkpoint and adjoint tables (257 jobs) are the most one call computes."""
+    p = 64
+    Q = workloads.qubos(1, n, 3300 + n)
+    g, b = workloads.params(1, p, 3400 + n, lead=(1,))
+    g, b = g * 0.1, b * 0.1
+    print(f"grad case prec={prec} n={n} p={p}", flush=True)
+    e, dg, db = api.grad(cuda(Q), cuda(g), cuda(b), prec=prec)
+    eo, dgo, dbo = oracle.grad(Q[0], g[0], b[0])
+    cm = cmax(Q[0])
+    tol = 1e-10 * max(1.0, cm) if prec == "c128" else 1e-5 * cm * p
+    assert np.max(np.abs(dg.cpu().numpy()[0] - dgo)) <= tol
+    assert np.max(np.abs(db.cpu().numpy()[0] - dbo)) <= tol
+    assert abs(e.cpu().numpy()[0] - eo).max() <= (1e-10 * max(1.0, cm) if prec == "c128" else 1e-5 * cm)
+
+
 @pytest.mark.parametrize("n,p", [(9, 2), (16, 3)])
 def test_grad_matches_central_differences(api, n, p):
     Q = workloads.qubo(n, 3200 + n)

@@ -75,6 +75,13 @@ def test_multipass_state_and_expect(api, n, p, prec):
     run_case(api, n, p, S=2, prec=prec, B=2 if n < 20 else 1)
 
 
+@pytest.mark.parametrize("prec,n", [("c64", 15), ("c128", 14)])
+def test_max_layers_state_and_expect(api, prec, n):
+    """QAOA_MAX_P = 64 layers on register tiles (2p + 1 = 129 passes, all their
+    tables from one launch)."""
+    run_case(api, n, 64, S=2, prec=prec)
+
+
 @pytest.mark.parametrize("n,p", [(23, 2), (25, 3)])
 def test_multiset_c128_state(api, n, p):
     """complex128 register tiles: two sets up to n = 24, three beyond (with a
