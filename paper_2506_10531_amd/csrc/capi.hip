@@ -18,8 +18,8 @@
 
 namespace dq {
 
-static_assert(MAX_TAB_JOBS >= 2 * (2 * QAOA_MAX_P + 1) - 1,
-              "a two-set register-tile gradient at QAOA_MAX_P layers fits the table jobs");
+static_assert(MAX_TAB_JOBS >= 3 * QAOA_MAX_P + 1,
+              "a four-set forward plan at QAOA_MAX_P layers fits the table jobs");
 
 // ---- errors -------------------------------------------------------------------
 

@@ -121,11 +121,12 @@ struct TabJob {
   int8_t kind, c, a, flip, kfl, neg;
   int8_t pad[2];
 };
-// The most table jobs of one call: a register-tile gradient on two qubit
-// sets at 64 layers has 2p + 1 passes, each with a checkpoint and an adjoint
-// job but the last, i.e. 2 (2p + 1) - 1 = 257.  The list travels as a kernel
-// argument (8 bytes a job).
-constexpr int MAX_TAB_JOBS = 257;
+// The most table jobs of one call.  A forward plan on m qubit sets has
+// p (m - 1) + 1 passes, one job each: at most 3p + 1 = 193 at 64 layers
+// (m <= 4).  A register-tile gradient runs on two sets: p + 1 passes, a
+// checkpoint and an adjoint job for each but the last, 2p + 1 = 129.  The
+// list travels as a kernel argument (8 bytes a job).
+constexpr int MAX_TAB_JOBS = 193;
 struct TabJobs {
   int njobs;
   TabJob job[MAX_TAB_JOBS];

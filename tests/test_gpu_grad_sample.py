@@ -61,8 +61,9 @@ def test_grad_matches_oracle(api, prec, n, p):
 
 @pytest.mark.parametrize("prec,n", [("c64", 14), ("c128", 13)])
 def test_grad_at_max_layers(api, prec, n):
-    """QAOA_MAX_P = 64 layers on register tiles: 2p + 1 = 129 passes, whose
-    checkpoint and adjoint tables (257 jobs) are the most one call computes."""
+    """QAOA_MAX_P = 64 layers on register tiles: p + 1 = 65 passes on two
+    qubit sets, whose checkpoint and adjoint tables make 2p + 1 = 129 jobs of
+    one tables launch."""
     p = 64
     Q = workloads.qubos(1, n, 3300 + n)
     g, b = workloads.params(1, p, 3400 + n, lead=(1,))

@@ -77,8 +77,8 @@ def test_multipass_state_and_expect(api, n, p, prec):
 
 @pytest.mark.parametrize("prec,n", [("c64", 15), ("c128", 14)])
 def test_max_layers_state_and_expect(api, prec, n):
-    """QAOA_MAX_P = 64 layers on register tiles (2p + 1 = 129 passes, all their
-    tables from one launch)."""
+    """QAOA_MAX_P = 64 layers on register tiles (p + 1 = 65 passes on two
+    qubit sets, all their tables from one launch)."""
     run_case(api, n, 64, S=2, prec=prec)
 
 

@@ -145,3 +145,17 @@ def test_large_state_bit_partition(hctx, n):
             for i, b in enumerate(sorted(blk)):
                 assert dep_block(1 << i, d) == 1 << b
             assert dep_local((1 << d["k"]) - 1, d) == sum(1 << b for b in tb)
+
+
+@pytest.mark.parametrize("prec,grad", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_table_jobs_fit_at_max_layers(hctx, prec, grad):
+    """One tables launch serves a register-tile call: one job per forward pass,
+    a checkpoint and an adjoint job per gradient pass but the last.  At
+    QAOA_MAX_P = 64 layers every plan's list fits the 193 jobs the library
+    holds."""
+    for n in range(1, 35):
+        ps = passes(hctx, prec, n, 64, grad)
+        if ps[0]["kind"] == 0:
+            continue
+        jobs = 2 * len(ps) - 1 if grad else len(ps)
+        assert jobs <= 193, (n, jobs)
