@@ -227,6 +227,8 @@ typedef struct {
   long long steps;      /* batched steps executed */
   int pending, active;  /* right now */
   size_t bytes_in_use;  /* device bytes held by resident requests */
+  int peak_active;      /* most requests resident at once since creation */
+  size_t peak_bytes;    /* most device bytes held by resident requests */
 } qaoa_queue_stats;
 
 int qaoa_queue_create(qaoa_ctx* ctx, const qaoa_queue_opts* opts,

@@ -101,7 +101,8 @@ class QueueStats(ctypes.Structure):
                 ("completed", ctypes.c_longlong), ("cancelled", ctypes.c_longlong),
                 ("rejected", ctypes.c_longlong), ("steps", ctypes.c_longlong),
                 ("pending", ctypes.c_int), ("active", ctypes.c_int),
-                ("bytes_in_use", ctypes.c_size_t)]
+                ("bytes_in_use", ctypes.c_size_t), ("peak_active", ctypes.c_int),
+                ("peak_bytes", ctypes.c_size_t)]
 
 
 _lib = None

@@ -454,8 +454,11 @@ void qaoa_queue::run() {
           r->res.t_admit_ns = now_ns();
           st.admitted++;
         }
-        bool any = false;
-        for (Request* r : slots) any |= (r != nullptr);
+        int resident = 0;
+        for (Request* r : slots) resident += r != nullptr;
+        st.peak_active = std::max(st.peak_active, resident);
+        st.peak_bytes = std::max(st.peak_bytes, in_use);
+        const bool any = resident > 0;
         if (stop) return;
         if (any) break;
         cv_sched.wait(lk);

@@ -237,3 +237,33 @@ def test_traversal_arguments(hctx):
                dict(k=101), dict(m=0), dict(ptrs=(0, 1, 1, 1)), dict(ptrs=(1, 0, 1, 1)),
                dict(ptrs=(1, 1, 0, 1)), dict(ptrs=(1, 1, 1, 0))):
         assert call(**kw) == _lib.ERR_INVALID_ARG, kw
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    """Every structure the binding passes through the C ABI has the size and
+    field offsets of its typedef in include/dqaoa.h (compiled here with gcc)."""
+    import shutil
+    import subprocess
+    from paper_2506_10531_amd import _lib
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    pairs = [(_lib.PlanInfo, "qaoa_plan_info"), (_lib.QueueOpts, "qaoa_queue_opts"),
+             (_lib.SolveReq, "qaoa_solve_req"), (_lib.SolveResult, "qaoa_solve_result"),
+             (_lib.CycleStats, "qaoa_cycle_stats"), (_lib.QueueStats, "qaoa_queue_stats")]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "dqaoa.h"', "int main(void) {"]
+    want = []
+    for cls, cname in pairs:
+        lines.append(f'  printf("%zu\\n", sizeof({cname}));')
+        want.append(ctypes.sizeof(cls))
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({cname}, {f}));')
+            want.append(getattr(cls, f).offset)
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert got == want

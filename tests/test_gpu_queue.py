@@ -114,18 +114,15 @@ def test_admission_respects_budget(serve):
     one = ctx.plan("c64", 1, 18, p, 1, grad=True)["scratch_bytes"]
     with serve.SolveQueue(prec="c64", p=p, evals=3, shots=16, max_slots=8,
                           hbm_budget=int(2.6 * one) + (8 << 20)) as q:
+        budget = int(2.6 * one) + (8 << 20)
         ts = [q.submit(Q, g[0], b[0], i) for i in range(5)]
-        peak = 0
-        deadline = time.time() + 60
-        while True:
-            st = q.stats()
-            peak = max(peak, st["active"])
-            if st["completed"] == 5:
-                break
-            assert time.time() < deadline, st
-            time.sleep(0.002)
-        assert 1 <= peak <= 2, peak
         rs = [q.wait(t) for t in ts]
+        # the scheduler's own high-water marks (sampling the current count
+        # from here can miss short requests altogether)
+        st = q.stats()
+        assert st["completed"] == 5, st
+        assert 1 <= st["peak_active"] <= 2, st
+        assert st["peak_bytes"] <= budget, st
     # FIFO: admission times are ordered by submission
     adm = [r["t_admit_ns"] for r in rs]
     assert adm == sorted(adm)
