@@ -3,7 +3,8 @@ oracle (complex64 and complex128), n = 26 against the oracle, and n = 32
 (a 32 GiB complex64 state, too large for the oracle's host memory budget)
 through properties that hold at any size: beta = 0 leaves the distribution
 uniform so <C> = (1'Q1 + tr Q)/4, unit norm, the p = 1 closed form, and the
-diagonal-Q product formula."""
+diagonal-Q product formula; the largest states (n = 34 complex64, n = 33
+complex128, 128 GiB each) against the p = 1 closed form."""
 import numpy as np
 import pytest
 
@@ -125,6 +126,23 @@ def test_three_sets_diagonal_q_p3(api, n):
     e = api.expect(cuda(np.diag(d)), cuda(g), cuda(b), prec="c64").cpu().numpy()[0]
     ref = dense_ref.diagonal_expect(d, g[0], b[0])
     assert abs(e[0] - ref) <= 1e-5 * np.abs(d).sum(), (e[0], ref)
+
+
+@pytest.mark.parametrize("prec,n", [("c64", 34), ("c128", 33)])
+def test_max_size_p1_closed_form(api, prec, n):
+    """The largest states: n = QAOA_MAX_N = 34 in complex64 (a 128 GiB state;
+    sets of 14, 10 and 10 qubits, the kind-2 tiles on 128-byte runs) and
+    n = 33 in complex128 (128 GiB; 64-byte runs)."""
+    Q = workloads.qubo(n, 90 + n)
+    g, b = workloads.params(1, 1, 95 + n)
+    print(f"n={n} {prec} p=1 closed form", flush=True)
+    e, nr = api.expect(cuda(Q), cuda(g), cuda(b), prec=prec, norm=True)
+    e, nr = float(e.cpu().numpy()[0][0]), float(nr.cpu().numpy()[0][0])
+    cf = dense_ref.p1_closed_form(Q, g[0, 0], b[0, 0])
+    bound = _cmax_bound(Q)
+    tol = 1e-5 * bound if prec == "c64" else 1e-10 * max(1.0, bound)
+    assert abs(e - cf) <= tol, (e, cf)
+    assert abs(nr - 1.0) <= (1e-5 if prec == "c64" else 1e-12), nr
 
 
 def test_large_n32_four_sets_runs_and_is_normalised(api):
