@@ -11,13 +11,18 @@
 //    free and the request's device bytes fit in the queue's HBM budget.
 //  * An admitted request keeps its Q, parameters and Adam moments in a
 //    device slot.  Every scheduler step advances all admitted requests by
-//    one evaluation: the requests are grouped by qubit count, each group is
-//    gathered into a contiguous batch, and one batched adjoint pipeline
-//    (forward passes, lambda = C psi, backward passes, fixed-order
-//    reductions) plus one Adam update runs per group, groups on separate
-//    streams.  Requests that finish their evaluations are sampled in the same
-//    step and completed.  Requests that arrive meanwhile join at the next
-//    step, so their work overlaps with the requests already running.
+//    the same number of evaluations: the requests are grouped by qubit
+//    count, each group is gathered into a contiguous batch, and one batched
+//    adjoint pipeline (forward passes, lambda = C psi, backward passes,
+//    fixed-order reductions) plus one Adam update runs per group and
+//    evaluation, groups on separate streams.  Requests that finish their
+//    evaluations are sampled in the same step and completed.  Requests that
+//    arrive meanwhile join at the next step, so their work overlaps with the
+//    requests already running.  A step makes one evaluation while a waiting
+//    request could be admitted at its end; otherwise up to
+//    MAX_EVALS_PER_STEP, no more than any of its requests has left, back to
+//    back with one host synchronisation for all of them (the host needs
+//    nothing between the evaluations of a request).
 //  * The big buffers (checkpoints, adjoint state, probabilities) exist only
 //    within a step; a request's byte charge is what its group needs for it
 //    during a step, so the sum over admitted requests bounds the arena.
@@ -53,6 +58,7 @@ namespace {
 
 constexpr int QN_MAX = 26;      // largest sub-QUBO a request may carry
 constexpr int NSTREAMS = 4;
+constexpr int MAX_EVALS_PER_STEP = 16;
 
 int64_t now_ns() {
   timespec ts;
@@ -240,6 +246,7 @@ void qaoa_queue::complete(Request* r, int status) {
 int qaoa_queue::step() {
   ++step_no;
   std::vector<Request*> act, fresh;
+  bool hold;  // no waiting request could be admitted now
   {
     std::lock_guard<std::mutex> lk(mu);
     for (Request* r : slots)
@@ -248,8 +255,19 @@ int qaoa_queue::step() {
         act.push_back(r);
         if (!r->uploaded) fresh.push_back(r);
       }
+    hold = pending.empty() || free_slots.empty() ||
+           in_use + reqs[pending.front()]->bytes > budget;
   }
   if (act.empty()) return QAOA_OK;
+  // evaluations per request this step
+  int K = hold ? MAX_EVALS_PER_STEP : 1;
+  bool evaluating = false;
+  for (Request* r : act)
+    if (r->evals_done < o.evals) {
+      K = std::min(K, o.evals - r->evals_done);
+      evaluating = true;
+    }
+  if (!evaluating) K = 1;
   const int p = o.p;
   hipStream_t s0 = streams[0];
   // upload newly admitted requests: Q, gamma0, beta0; zero Adam state
@@ -285,7 +303,7 @@ int qaoa_queue::step() {
     g.n = r->n;
     if (r->evals_done < o.evals) {
       g.ev.push_back(r);
-      if (r->evals_done + 1 == o.evals) g.sm.push_back(r);
+      if (r->evals_done + K == o.evals) g.sm.push_back(r);
     } else {
       g.sm.push_back(r);
     }
@@ -360,7 +378,7 @@ int qaoa_queue::step() {
     const int* ie = dIdx + idx_off[gi].first;
     const int* is = dIdx + idx_off[gi].second;
     auto A = [&](size_t i) { return base + g.cv.off[i]; };
-    if (nb) {
+    for (int k = 0; nb && k < K; ++k) {
       int rc = eval_group(g, ie, base, s);
       if (rc) return rc;
     }
@@ -405,7 +423,7 @@ int qaoa_queue::step() {
   gi = 0;
   for (auto& kv : groups) {
     GroupPlan& g = kv.second;
-    for (Request* r : g.ev) r->evals_done++;
+    for (Request* r : g.ev) r->evals_done += K;
     const int ns = (int)g.sm.size();
     const char* hr = hRes + g_res[gi];
     for (int i = 0; i < ns; ++i) {
