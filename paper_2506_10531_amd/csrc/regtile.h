@@ -891,12 +891,14 @@ fwd_kernel(FwdArgs A) {
   // the first pass starts from the uniform amplitude 2^{-n/2}: it folds into
   // the thread factor, and the phase factors become the amplitudes
   if (PT == P_FIRST) sr *= exp2(-0.5 * (double)n), si *= exp2(-0.5 * (double)n);
-  if (PHASE) P = phase_factors<G, PL>(&T, fl, cblk, lane, wave, cf[d.jb].gp, sr, si);
   bool sw = f0;  // tile bit 0 is flipped
   if (LEAD) {
     const LayerCoef& L = cf[d.lead];
     G::template lead<KIND, MIXLO>(v, buf, lane, wave, (S)mix_t(L, false), L.mode != 0);
   }
+  // formed after the lead half-mixer: formed before it, the factors would
+  // hold registers through its rounds and transposes
+  if (PHASE) P = phase_factors<G, PL>(&T, fl, cblk, lane, wave, cf[d.jb].gp, sr, si);
   if (PHASE) {
     const LayerCoef& L = cf[d.jb];
     if (PT == P_FIRST) init_phase<G>(v, KF, P);
