@@ -210,6 +210,19 @@ def test_traversal_golden_shape(api, mode):
         assert np.array_equal(ch.cpu().numpy(), oracle_traversal(Q, imp, order, 7, k, mode)), k
 
 
+def test_traversal_weighted_golden(api):
+    # unequal, signed, asymmetric couplings: BFS takes neighbours by
+    # |Q_ij + Q_ji|, strongest first (tests/golden/traversal_weighted.txt)
+    from tests.test_traversal_oracle import GOLD_W, _golden, weighted_example_q
+    g = _golden(GOLD_W)
+    Q = weighted_example_q()
+    imp = np.array(g["impact"], dtype=np.float64)
+    order = cycle.rank(imp)
+    for k in range(2, 9):
+        ch = api.traversal_choices(cuda(Q), cuda(imp), cuda(order, torch.int32), 1, k, "bfs")
+        assert ch.cpu().numpy()[0].tolist() == [int(v) for v in g[f"bfs_k{k}"]], k
+
+
 @pytest.mark.parametrize("mode", ["bfs", "pfs"])
 @pytest.mark.parametrize("N,m,k,kind", [(200, 100, 12, "maxcut"), (300, 40, 20, "dense"),
                                         (64, 30, 16, "blocks"), (1000, 500, 12, "maxcut")])

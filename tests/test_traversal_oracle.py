@@ -14,11 +14,13 @@ from oracle.traversal import bfs_window, pfs_window, traversal_choices
 from paper_2506_10531_amd import workloads
 
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "traversal_example.txt")
+GOLD_W = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "traversal_weighted.txt")
 
 
-def _golden():
+def _golden(path=GOLD):
     rec = {}
-    for line in open(GOLD):
+    for line in open(path):
         line = line.split("#")[0].strip()
         if line:
             k, v = line.split("=")
@@ -43,6 +45,25 @@ def test_hand_example():
     assert pfs_window(Q, imp, 0, 4) == [int(v) for v in g["pfs_k4"]]
     assert bfs_window(Q, imp, 0, 6) == [int(v) for v in g["bfs_k6"]]
     assert pfs_window(Q, imp, 0, 6) == [int(v) for v in g["pfs_k6"]]
+
+
+def weighted_example_q():
+    """The eight-variable QUBO of tests/golden/traversal_weighted.txt: unequal,
+    signed and asymmetric couplings (Q_ij, Q_ji)."""
+    Q = np.zeros((8, 8))
+    for (a, b), (qab, qba) in {(0, 1): (0.1, 0.1), (0, 3): (1.0, 0.0), (0, 5): (-1.2, 0.6),
+                               (3, 4): (0.3, 0.0), (3, 6): (0.0, -0.9), (5, 2): (0.4, 0.4),
+                               (1, 7): (0.25, 0.25)}.items():
+        Q[a, b], Q[b, a] = qab, qba
+    return Q
+
+
+def test_bfs_strongest_first_by_coupling_sum():
+    g = _golden(GOLD_W)
+    imp = np.array(g["impact"])
+    Q = weighted_example_q()
+    for k in range(2, 9):
+        assert bfs_window(Q, imp, 0, k) == [int(v) for v in g[f"bfs_k{k}"]], k
 
 
 @pytest.mark.parametrize("mode", ["bfs", "pfs"])
