@@ -50,13 +50,20 @@ def _rebase(x0, f0, D, fv, j):
     return x0, f0, D, fv
 
 
-def cobyla_min(f, x0, rhobeg=0.5, rhoend=1e-6, maxfun=200):
-    """Minimise f from x0 by the steps above.  Returns (x, f(x), nfev)."""
+def cobyla_min(f, x0, rhobeg=0.5, rhoend=1e-6, maxfun=200, trace=None):
+    """Minimise f from x0 by the steps above.  Returns (x, f(x), nfev).
+
+    If ``trace`` is a list, one record per evaluation is appended: the kind
+    of point ("start", "init", "geometry", "trust"), the point, its value,
+    the vertex it replaced (-1 for start/init), whether it became the
+    optimal vertex and whether rho shrank after it."""
     x0 = np.array(x0, dtype=np.float64)
     n = x0.size
     rho = float(rhobeg)
+    rec = (lambda **kw: trace.append(kw)) if trace is not None else (lambda **kw: None)
     f0 = f(x0)
     nfev = 1
+    rec(kind="start", x=x0.copy(), f=f0, j=-1, rebase=False, shrink=False)
     D = rho * np.eye(n)
     fv = np.empty(n)
     for i in range(n):
@@ -64,7 +71,10 @@ def cobyla_min(f, x0, rhobeg=0.5, rhoend=1e-6, maxfun=200):
             return x0, f0, nfev
         fv[i] = f(x0 + D[:, i])
         nfev += 1
+        rec(kind="init", x=x0 + D[:, i], f=fv[i], j=-1, rebase=False, shrink=False)
     best = int(np.argmin(fv))
+    if trace is not None:
+        trace[-1]["rebase"] = bool(fv[best] < f0)
     if fv[best] < f0:
         x0, f0, D, fv = _rebase(x0, f0, D, fv, best)
     while nfev < maxfun:
@@ -84,6 +94,7 @@ def cobyla_min(f, x0, rhobeg=0.5, rhoend=1e-6, maxfun=200):
             nfev += 1
             D[:, j] = d
             fv[j] = fn
+            rec(kind="geometry", x=x0 + d, f=fn, j=j, rebase=bool(fn < f0), shrink=False)
             if fn < f0:
                 x0, f0, D, fv = _rebase(x0, f0, D, fv, j)
             continue
@@ -95,6 +106,8 @@ def cobyla_min(f, x0, rhobeg=0.5, rhoend=1e-6, maxfun=200):
             nfev += 1
             ratio = (f0 - fn) / (rho * gn)
             j = int(np.argmax(np.abs(A @ d)))
+            rec(kind="trust", x=x0 + d, f=fn, j=j, rebase=bool(fn < f0),
+                shrink=bool(ratio < ETA))
             D[:, j] = d
             fv[j] = fn
             if fn < f0:
@@ -109,10 +122,10 @@ def cobyla_min(f, x0, rhobeg=0.5, rhoend=1e-6, maxfun=200):
     return x0, f0, nfev
 
 
-def cobyla_loop(Q, theta0, rhobeg=0.5, rhoend=1e-6, maxfun=200):
+def cobyla_loop(Q, theta0, rhobeg=0.5, rhoend=1e-6, maxfun=200, trace=None):
     """The paper's loop on one sub-QUBO: (theta, <C>, nfev) for theta0 =
     (gamma_1..p, beta_1..p), the objective being the complex128 oracle's
-    exact <C>."""
+    exact <C>.  ``trace`` as in cobyla_min."""
     theta0 = np.asarray(theta0, dtype=np.float64)
     p = theta0.size // 2
 
@@ -120,4 +133,4 @@ def cobyla_loop(Q, theta0, rhobeg=0.5, rhoend=1e-6, maxfun=200):
         e, _, _ = expect(Q, x[None, :p], x[None, p:])
         return float(e[0])
 
-    return cobyla_min(fq, theta0, rhobeg, rhoend, maxfun)
+    return cobyla_min(fq, theta0, rhobeg, rhoend, maxfun, trace)

@@ -1,9 +1,15 @@
 """Pins of the oracle's COBYLA-type loop (oracle/cobyla_loop.py) by cases
-whose optimum is known without it: a one-variable QUBO, whose p = 1
-objective is q times the probability of z = 1 (minimum min(0, q)); convex
-quadratics with a known minimiser, where SciPy's COBYLA (Powell's reference
-code) reaches the same minimum; refinement of a dense objective grid; and
-the evaluation budget."""
+whose optimum is known without it: two hand-worked trajectories
+(tests/golden/cobyla_trajectory.txt) that fix every step rule (the initial
+simplex, re-basing on a better vertex, trust steps and the vertex they drop,
+geometry steps for a far and a flat vertex with both signs of g.v, rho
+halving, the clamp to rhoend and the stop); a one-variable QUBO, whose
+p = 1 objective is q times the probability of z = 1 (minimum min(0, q));
+convex quadratics with a known minimiser, where SciPy's COBYLA (Powell's
+reference code) reaches the same minimum; refinement of a dense objective
+grid; and the evaluation budget."""
+import os
+
 import numpy as np
 import pytest
 from scipy.optimize import minimize
@@ -62,3 +68,58 @@ def test_budget_and_descent():
     assert nfev == 7 and f <= e0
     _, f, nfev = cobyla_loop(Q, th0, maxfun=300)
     assert f <= e0 and nfev <= 300
+
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cobyla_trajectory.txt")
+
+
+def golden_cases():
+    cases, cur = [], None
+    for line in open(GOLD):
+        line = line.split("#")[0].strip()
+        if not line:
+            continue
+        if line.startswith("case "):
+            cur = {"name": line.split()[1], "evals": []}
+            cases.append(cur)
+        elif line.startswith("eval "):
+            _, _, kind, x, y, fx = line.split()
+            cur["evals"].append((kind, float(x), float(y), float(fx)))
+        elif line.startswith("final "):
+            _, x, y, fx, nfev = line.split()
+            cur["final"] = (float(x), float(y), float(fx), int(nfev))
+        else:
+            k, v = line.split("=")
+            cur[k.strip()] = [float(t) for t in v.split()]
+    return cases
+
+
+@pytest.mark.parametrize("case", golden_cases(), ids=lambda c: c["name"])
+def test_hand_worked_trajectory(case):
+    a, b = case["minimiser"]
+    h = case["weight"][0]
+
+    def f(x):
+        return (x[0] - a) ** 2 + h * (x[1] - b) ** 2
+
+    trace = []
+    x, fx, nfev = cobyla_min(f, np.array(case["x0"]), rhobeg=case["rhobeg"][0],
+                             rhoend=case["rhoend"][0], maxfun=int(case["maxfun"][0]),
+                             trace=trace)
+    assert len(trace) == len(case["evals"]) == nfev
+    for k, (rec, (kind, gx, gy, gf)) in enumerate(zip(trace, case["evals"])):
+        assert rec["kind"] == kind, k
+        assert abs(rec["x"][0] - gx) <= 1e-12 and abs(rec["x"][1] - gy) <= 1e-12, k
+        assert abs(rec["f"] - gf) <= 1e-12 * max(1.0, abs(gf)), k
+    fxg, fyg, ffg, nfg = case["final"]
+    assert nfev == nfg
+    assert abs(x[0] - fxg) <= 1e-12 and abs(x[1] - fyg) <= 1e-12 and abs(fx - ffg) <= 1e-12
+
+
+def test_golden_covers_every_rule():
+    kinds = [{e[0] for e in c["evals"]} for c in golden_cases()]
+    assert set.union(*kinds) == {"start", "init", "trust", "geometry"}
+    text = open(GOLD).read()
+    for event in ("becomes x0", "drops vertex", "rho ->", "rho is rhoend: stop",
+                  "(|d", "(face distance", "g.v = -"):
+        assert event in text, event
