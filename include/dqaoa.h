@@ -195,7 +195,8 @@ int qaoa_profile_read(qaoa_ctx* ctx, int reset, long long* launches,
 typedef struct {
   int max_slots;        /* requests resident at once (>= 1) */
   int max_pending;      /* queued requests before qaoa_submit reports QUEUE_FULL */
-  size_t hbm_budget;    /* device bytes for resident requests (0 = context budget) */
+  size_t hbm_budget;    /* device bytes for resident requests (0: half the context
+                           budget, at most 80% of the memory free at creation) */
   int prec;             /* QAOA_C64 or QAOA_C128 */
   int p;                /* layers */
   int evals;            /* Adam steps per solve (>= 0) */
@@ -205,7 +206,7 @@ typedef struct {
 } qaoa_queue_opts;
 
 typedef struct {
-  int n;                /* qubits (variables of the sub-QUBO), 1..22 */
+  int n;                /* qubits (variables of the sub-QUBO), 1..26 */
   const double* Q;      /* host [n][n] FP64; copied by qaoa_submit */
   const double* gamma0; /* host [p] initial gammas; copied */
   const double* beta0;  /* host [p] initial betas; copied */
@@ -264,13 +265,15 @@ int qaoa_queue_get_stats(qaoa_queue* q, qaoa_queue_stats* out);
  * evaluations per problem.  Every round, the points of all running
  * optimisers are evaluated by one qaoa_expect call.  Outputs (host): theta
  * [B][2p] the best point, expect [B] <C> there, nfev [B] evaluations
- * (nullable), rounds [1] batched calls (nullable).  Requires rhobeg >=
- * rhoend > 0, maxfun >= 1.  Blocking (synchronises stream); allocates its
- * device buffers for the call. */
+ * (nullable), rounds [1] batched calls (nullable), trace [B][maxfun][2p + 1]
+ * (nullable): record k of problem b is its k-th evaluated point followed by
+ * the <C> found there (records from nfev[b] on are left untouched).
+ * Requires rhobeg >= rhoend > 0, maxfun >= 1.  Blocking (synchronises
+ * stream); allocates its device buffers for the call. */
 int qaoa_cobyla(qaoa_ctx* ctx, int prec, int B, int n, int p, const double* Q,
                 const double* theta0, double rhobeg, double rhoend, int maxfun,
                 double* theta, double* expect, int* nfev, int* rounds,
-                qaoa_stream_t stream);
+                double* trace, qaoa_stream_t stream);
 
 /* Sampled objective of a sampler-based QAOA (the measurement of Sec. IV):
  * out[b] = CVaR_alpha of the shot energies cz[b][0..shots) (device, FP64,

@@ -18,11 +18,13 @@
 //    evaluation, groups on separate streams.  Requests that finish their
 //    evaluations are sampled in the same step and completed.  Requests that
 //    arrive meanwhile join at the next step, so their work overlaps with the
-//    requests already running.  A step makes one evaluation while a waiting
-//    request could be admitted at its end; otherwise up to
-//    MAX_EVALS_PER_STEP, no more than any of its requests has left, back to
-//    back with one host synchronisation for all of them (the host needs
-//    nothing between the evaluations of a request).
+//    requests already running.  A step makes up to MAX_EVALS_PER_STEP
+//    evaluations, no more than any of its requests has left, enqueued round
+//    by round with at most two rounds in flight; before each further round
+//    the scheduler looks for a waiting request that a free slot and the
+//    byte budget could now take (or a cancellation), and if there is one it
+//    ends the step after the rounds already enqueued, so an arrival waits
+//    at most about two evaluations while the GPU stays busy.
 //  * The big buffers (checkpoints, adjoint state, probabilities) exist only
 //    within a step; a request's byte charge is what its group needs for it
 //    during a step, so the sum over admitted requests bounds the arena.
@@ -118,6 +120,7 @@ struct qaoa_queue {
   // device state
   hipStream_t streams[NSTREAMS] = {};
   hipEvent_t ev_up = nullptr;
+  hipEvent_t ev_round[2][NSTREAMS] = {};  // the last two evaluation rounds per stream
   char* arena = nullptr;
   double *dQ = nullptr, *dG = nullptr, *dB = nullptr, *dM = nullptr, *dV = nullptr;
   uint64_t* dSeed = nullptr;
@@ -159,7 +162,17 @@ struct qaoa_queue {
   int eval_group(const GroupPlan& g, const int* ie, char* base, hipStream_t s);
   int enqueue_eval(const GroupPlan& g, const int* ie, char* base, hipStream_t s);
   void complete(Request* r, int status);
+  bool should_yield(const std::vector<Request*>& act);
 };
+
+// Called with the lock held: a waiting request that could be admitted right
+// now, or a cancelled request among those running, ends the step early.
+bool qaoa_queue::should_yield(const std::vector<Request*>& act) {
+  for (Request* r : act)
+    if (r->cancel) return true;
+  if (pending.empty() || free_slots.empty()) return false;
+  return in_use + reqs[pending.front()]->bytes <= budget;
+}
 
 // One evaluation of an n-group: gather its requests' Q and parameters,
 // the adjoint pipeline, the Adam update.  Kernels only (capturable).
@@ -246,7 +259,6 @@ void qaoa_queue::complete(Request* r, int status) {
 int qaoa_queue::step() {
   ++step_no;
   std::vector<Request*> act, fresh;
-  bool hold;  // no waiting request could be admitted now
   {
     std::lock_guard<std::mutex> lk(mu);
     for (Request* r : slots)
@@ -255,12 +267,10 @@ int qaoa_queue::step() {
         act.push_back(r);
         if (!r->uploaded) fresh.push_back(r);
       }
-    hold = pending.empty() || free_slots.empty() ||
-           in_use + reqs[pending.front()]->bytes > budget;
   }
   if (act.empty()) return QAOA_OK;
-  // evaluations per request this step
-  int K = hold ? MAX_EVALS_PER_STEP : 1;
+  // evaluations per request this step (fewer if an arrival ends it early)
+  int K = MAX_EVALS_PER_STEP;
   bool evaluating = false;
   for (Request* r : act)
     if (r->evals_done < o.evals) {
@@ -364,24 +374,59 @@ int qaoa_queue::step() {
     return set_error(QAOA_ERR_OUT_OF_MEMORY, "step needs %zu arena bytes of %zu", off, budget);
   if (res_off > hRes_bytes)
     return set_error(QAOA_ERR_OUT_OF_MEMORY, "step results exceed the staging buffer");
-  // launch every group on its stream
+  // evaluation rounds: round k enqueues one evaluation of every group on the
+  // group's stream; from round 2 on, the host first waits for round k - 2 and
+  // ends the step there if a waiting request could now be admitted
   gi = 0;
   for (auto& kv : groups) {
-    GroupPlan& g = kv.second;
     hipStream_t s = streams[gi % NSTREAMS];
+    (void)kv;
     if (s != s0) {
       e = hipStreamWaitEvent(s, ev_up, 0);
       if (e != hipSuccess) return hip_error(e, "hipStreamWaitEvent");
     }
+    ++gi;
+  }
+  const int nused = std::min<int>((int)groups.size(), NSTREAMS);
+  int Kdone = K;
+  for (int k = 0; k < K; ++k) {
+    if (k >= 2) {
+      for (int i = 0; i < nused; ++i) {
+        e = hipEventSynchronize(ev_round[k % 2][i]);
+        if (e != hipSuccess) return hip_error(e, "hipEventSynchronize");
+      }
+      std::lock_guard<std::mutex> lk(mu);
+      if (should_yield(act)) {
+        Kdone = k;
+        break;
+      }
+    }
+    gi = 0;
+    for (auto& kv : groups) {
+      GroupPlan& g = kv.second;
+      if (!g.ev.empty()) {
+        int rc = eval_group(g, dIdx + idx_off[gi].first, arena + g_base[gi],
+                            streams[gi % NSTREAMS]);
+        if (rc) return rc;
+      }
+      ++gi;
+    }
+    for (int i = 0; i < nused; ++i) {
+      e = hipEventRecord(ev_round[k % 2][i], streams[i]);
+      if (e != hipSuccess) return hip_error(e, "hipEventRecord");
+    }
+  }
+  // requests reach their last evaluation only when the step ran all K rounds
+  // (K is the fewest evaluations any request has left)
+  const bool sampled = Kdone == K;
+  gi = 0;
+  for (auto& kv : groups) {
+    GroupPlan& g = kv.second;
+    hipStream_t s = streams[gi % NSTREAMS];
     char* base = arena + g_base[gi];
-    const int n = g.n, nb = (int)g.ev.size(), ns = (int)g.sm.size();
-    const int* ie = dIdx + idx_off[gi].first;
+    const int n = g.n, ns = sampled ? (int)g.sm.size() : 0;
     const int* is = dIdx + idx_off[gi].second;
     auto A = [&](size_t i) { return base + g.cv.off[i]; };
-    for (int k = 0; nb && k < K; ++k) {
-      int rc = eval_group(g, ie, base, s);
-      if (rc) return rc;
-    }
     if (ns) {
       double *Q = (double*)A(g.iQs), *gg = (double*)A(g.iGs), *bb = (double*)A(g.iBs);
       uint64_t* z = (uint64_t*)A(g.iZ);
@@ -423,8 +468,8 @@ int qaoa_queue::step() {
   gi = 0;
   for (auto& kv : groups) {
     GroupPlan& g = kv.second;
-    for (Request* r : g.ev) r->evals_done += K;
-    const int ns = (int)g.sm.size();
+    for (Request* r : g.ev) r->evals_done += Kdone;
+    const int ns = sampled ? (int)g.sm.size() : 0;
     const char* hr = hRes + g_res[gi];
     for (int i = 0; i < ns; ++i) {
       Request* r = g.sm[i];
@@ -520,17 +565,25 @@ int qaoa_queue_create(qaoa_ctx* ctx, const qaoa_queue_opts* opts, qaoa_queue** o
   q->o = o;
   if (!o.batched) q->o.max_slots = 1;
   q->device = dev;
-  q->budget = o.hbm_budget ? o.hbm_budget : ctx_budget(ctx) / 2;
   {  // DQAOA_QUEUE_GRAPHS=0 runs every evaluation step eagerly
     const char* v = getenv("DQAOA_QUEUE_GRAPHS");
     q->use_graphs = !(v && strcmp(v, "0") == 0);
   }
   const int S = q->o.max_slots, p = o.p;
   if (hipSetDevice(dev) != hipSuccess) return set_error(QAOA_ERR_HIP, "hipSetDevice");
+  q->budget = o.hbm_budget;
+  if (!q->budget) {  // half the context's budget, within what is free right now
+    size_t fr = 0, tot = 0;
+    q->budget = ctx_budget(ctx) / 2;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) q->budget = std::min(q->budget, fr / 10 * 8);
+  }
   hipError_t e = hipSuccess;
   for (int i = 0; i < NSTREAMS && e == hipSuccess; ++i)
     e = hipStreamCreateWithFlags(&q->streams[i], hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&q->ev_up, hipEventDisableTiming);
+  for (int r = 0; r < 2; ++r)
+    for (int i = 0; i < NSTREAMS && e == hipSuccess; ++i)
+      e = hipEventCreateWithFlags(&q->ev_round[r][i], hipEventDisableTiming);
   if (e == hipSuccess) e = hipMalloc((void**)&q->arena, q->budget);
   if (e == hipSuccess) e = hipMalloc((void**)&q->dQ, sizeof(double) * S * QN_MAX * QN_MAX);
   if (e == hipSuccess) e = hipMalloc((void**)&q->dG, sizeof(double) * S * p);
@@ -576,6 +629,9 @@ int qaoa_queue_destroy(qaoa_queue* q) {
   for (int i = 0; i < NSTREAMS; ++i)
     if (q->streams[i]) (void)hipStreamDestroy(q->streams[i]);
   if (q->ev_up) (void)hipEventDestroy(q->ev_up);
+  for (int r = 0; r < 2; ++r)
+    for (int i = 0; i < NSTREAMS; ++i)
+      if (q->ev_round[r][i]) (void)hipEventDestroy(q->ev_round[r][i]);
   void* dev[] = {q->arena, q->dQ, q->dG, q->dB, q->dM, q->dV, q->dT, q->dSeed, q->dIdx};
   for (void* ptr : dev)
     if (ptr) (void)hipFree(ptr);

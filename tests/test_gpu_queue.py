@@ -1,5 +1,6 @@
-"""The solve queue on the GPU: results against the oracle's solve loop, the
-alone-versus-mix identity, FIFO admission, backpressure, budget rejection and
+"""The solve queue on the GPU: results against the oracle's solve loop in
+both precisions, the alone-versus-mix identity, FIFO admission, admission of
+an arrival while a long step runs, backpressure, budget rejection and
 cancellation."""
 import time
 
@@ -45,6 +46,62 @@ def test_queue_matches_oracle_solve_loop(serve):
         assert mism <= 2, mism
         assert r["best_c"] <= o["best_c"] + 1e-12 or mism > 0
         assert r["t_submit_ns"] <= r["t_admit_ns"] <= r["t_done_ns"]
+
+
+def test_queue_complex64_matches_oracle_solve_loop(serve):
+    """Complex64 solves after 5 Adam evaluations against the complex128
+    oracle loop: <C> within the complex64 tolerance 1e-5 max|C| (Adam
+    normalises each step, so a gradient error dg moves theta by about
+    lr dg / |g| and <C> by about lr dg, well inside it), parameters within
+    1e-3, and samples equal except near CDF boundaries."""
+    p, evals, shots = 3, 5, 512
+    rs = reqs(8, p, 60, n_lo=8, n_hi=22)
+    with serve.SolveQueue(prec="c64", p=p, evals=evals, shots=shots, max_slots=8) as q:
+        tickets = [q.submit(Q, g, b, sd) for Q, g, b, sd in rs]
+        res = [q.wait(t, timeout_s=120) for t in tickets]
+    for (Q, g, b, sd), r in zip(rs, res):
+        n = Q.shape[0]
+        print(f"queue c64 oracle n={n}", flush=True)
+        assert r["status"] == 0
+        o = oracle.adam_solve(Q, g, b, evals=evals, shots=shots, seed=sd)
+        cmax = float(np.max(np.abs(oracle.cost_table(Q))))
+        dth = max(np.max(np.abs(r["gamma"] - o["gamma"])), np.max(np.abs(r["beta"] - o["beta"])))
+        print(f"  |d<C>| = {abs(r['expect'] - o['expect']):.2e}  max|C| = {cmax:.2f}  "
+              f"|dtheta| = {dth:.2e}", flush=True)
+        assert abs(r["expect"] - o["expect"]) <= 1e-5 * cmax
+        assert dth <= 1e-3
+        mism = int((r["samples"] != o["z"]).sum())
+        assert mism <= shots // 100, mism
+
+
+def test_arrival_admitted_within_a_few_evaluations(serve):
+    """A request that arrives while a long step runs and finds a free slot
+    joins after at most a few evaluations (the scheduler ends a step early
+    for it), not after the step's up to 16 evaluations."""
+    p, evals = 3, 240
+    long_q = [workloads.qubo(22, 70 + i) for i in range(8)]
+    g, b = workloads.params(9, p, 71)
+    small = workloads.qubo(12, 72)
+    with serve.SolveQueue(prec="c64", p=p, evals=evals, shots=64, max_slots=11) as q:
+        ts = [q.submit(Q, g[i], b[i], i) for i, Q in enumerate(long_q)]
+        deadline = time.time() + 60
+        while q.stats()["active"] != 8:
+            assert time.time() < deadline
+            time.sleep(0.001)
+        tks = []
+        for k in range(3):  # three arrivals while the long solves run
+            time.sleep(0.023 + 0.011 * k)
+            tks.append(q.submit(small, g[8], b[8], 100 + k))
+        rs = [q.wait(t, timeout_s=120) for t in tks]
+        rl = [q.wait(t, timeout_s=120) for t in ts]
+    assert all(r["status"] == 0 for r in rs + rl)
+    # the arrivals came while the long solves were still running
+    assert all(r["t_submit_ns"] < rl[0]["t_done_ns"] for r in rs)
+    waits = [r["t_admit_ns"] - r["t_submit_ns"] for r in rs]
+    per_eval = (rl[0]["t_done_ns"] - rl[0]["t_admit_ns"]) / evals
+    print(f"admission waits {[w / 1e6 for w in waits]} ms; one evaluation of the "
+          f"eight n=22 solves {per_eval / 1e6:.3f} ms", flush=True)
+    assert max(waits) <= 5 * per_eval + 2e6
 
 
 def _run(serve, items, **kw):
