@@ -151,7 +151,7 @@ def load():
     L.qaoa_cycle_workspace.argtypes = [i, i, i]
     L.qaoa_cvar.argtypes = [vp, i, i, dp, ctypes.c_double, dp, vp]
     L.qaoa_cobyla.argtypes = [vp, i, i, i, i, dp, dp, ctypes.c_double, ctypes.c_double, i,
-                              dp, dp, dp, dp, vp]
+                              dp, dp, dp, dp, dp, vp]
     L.qaoa_dqaoa_cycle.argtypes = [vp, vp, i, dp, dp, dp, dp, i, i, i, i, dp, dp, dp,
                                    u64, dp, ctypes.POINTER(CycleStats), vp]
     for name in EXPORTS:

@@ -331,11 +331,12 @@ def sampled_objective(Q, gammas, betas, shots: int, seed: int, alpha: float = 1.
 
 
 def cobyla(Q, theta0, rhobeg: float = 0.5, rhoend: float = 1e-6, maxfun: int = 200,
-           prec="c128", ctx=None):
+           prec="c128", trace: bool = False, ctx=None):
     """COBYLA-type minimisation of <C> over (gamma, beta) for every problem
     Q [B, n, n] (GPU float64) from theta0 [B, 2p] (host array), batched:
     every round of requests is one qaoa_expect (qaoa_cobyla).  Returns
-    dict(theta [B, 2p], expect [B], nfev [B], rounds)."""
+    dict(theta [B, 2p], expect [B], nfev [B], rounds), plus trace [B,
+    maxfun, 2p + 1] (each evaluated point and its <C>) if ``trace``."""
     import numpy as np
     Q = _dev(Q, "Q")
     if Q.dim() == 2:
@@ -349,10 +350,14 @@ def cobyla(Q, theta0, rhobeg: float = 0.5, rhoend: float = 1e-6, maxfun: int = 2
     th = np.empty_like(th0)
     e = np.empty(B)
     nf = np.empty(B, dtype=np.int32)
+    tr = np.full((B, int(maxfun), 2 * p + 1), np.nan) if trace else None
     r = ctypes.c_int(0)
-    cp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    cp = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
     _lib.check(_lib.load().qaoa_cobyla(ctx.h, _prec(prec), B, n, p, _ptr(Q), cp(th0),
                                        float(rhobeg), float(rhoend), int(maxfun), cp(th), cp(e),
                                        cp(nf), ctypes.cast(ctypes.pointer(r), ctypes.c_void_p),
-                                       _stream()))
-    return dict(theta=th, expect=e, nfev=nf, rounds=r.value)
+                                       cp(tr), _stream()))
+    out = dict(theta=th, expect=e, nfev=nf, rounds=r.value)
+    if trace:
+        out["trace"] = tr
+    return out

@@ -231,7 +231,7 @@ using namespace dq;
 extern "C" int qaoa_cobyla(qaoa_ctx* ctx, int prec, int B, int n, int p, const double* Q,
                            const double* theta0, double rhobeg, double rhoend, int maxfun,
                            double* theta, double* expect, int* nfev, int* rounds,
-                           qaoa_stream_t stream) {
+                           double* trace, qaoa_stream_t stream) {
   if (!ctx) return set_error(QAOA_ERR_INVALID_ARG, "ctx is NULL");
   if (prec != QAOA_C128 && prec != QAOA_C64)
     return set_error(QAOA_ERR_INVALID_ARG, "prec %d is not QAOA_C128 or QAOA_C64", prec);
@@ -280,6 +280,10 @@ extern "C" int qaoa_cobyla(qaoa_ctx* ctx, int prec, int B, int n, int p, const d
         hg[k * p + j] = x[j];
         hb[k * p + j] = x[p + j];
       }
+      if (trace) {  // the point of this problem's next evaluation
+        double* t = trace + ((size_t)act[k] * maxfun + opt[act[k]].nfev) * (m + 1);
+        for (int j = 0; j < m; ++j) t[j] = x[j];
+      }
     }
     const int Ba = (int)act.size();
     if (e == hipSuccess) e = hipMemcpyAsync(gd, hg.data(), (size_t)Ba * p * 8, hipMemcpyHostToDevice, s);
@@ -290,7 +294,10 @@ extern "C" int qaoa_cobyla(qaoa_ctx* ctx, int prec, int B, int n, int p, const d
     e = hipMemcpyAsync(he.data(), ed, (size_t)Ba * 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) break;
-    for (size_t k = 0; k < act.size(); ++k) opt[act[k]].tell(he[k]);
+    for (size_t k = 0; k < act.size(); ++k) {
+      if (trace) trace[((size_t)act[k] * maxfun + opt[act[k]].nfev) * (m + 1) + m] = he[k];
+      opt[act[k]].tell(he[k]);
+    }
     ++nr;
   }
   if (e != hipSuccess && rc == QAOA_OK) rc = hip_error(e, "cobyla rounds");

@@ -216,7 +216,8 @@ def test_cobyla_arguments(hctx):
 
     def call(prec=0, B=4, n=10, p=1, rb=0.5, re=1e-6, mf=100, ptrs=(1, 1, 1, 1)):
         q, t0, t, e = (_P(v) for v in ptrs)
-        return L.qaoa_cobyla(hctx, prec, B, n, p, q, t0, rb, re, mf, t, e, None, None, None)
+        return L.qaoa_cobyla(hctx, prec, B, n, p, q, t0, rb, re, mf, t, e, None, None, None,
+                             None)
     assert call() == _lib.ERR_NO_DEVICE
     for kw in (dict(prec=3), dict(B=0), dict(n=0), dict(n=35), dict(p=0), dict(p=65),
                dict(rb=1e-7, re=1e-6), dict(re=0.0), dict(rb=float("inf")), dict(mf=0),
