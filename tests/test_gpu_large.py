@@ -1,10 +1,18 @@
 """Large single states on the GPU: the n = 24 precision workload against the
-oracle (complex64 and complex128), n = 26 against the oracle, and n = 32
-(a 32 GiB complex64 state, too large for the oracle's host memory budget)
-through properties that hold at any size: beta = 0 leaves the distribution
-uniform so <C> = (1'Q1 + tr Q)/4, unit norm, the p = 1 closed form, and the
-diagonal-Q product formula; the largest states (n = 34 complex64, n = 33
-complex128, 128 GiB each) against the p = 1 closed form."""
+oracle (complex64 and complex128, all 16 sets), n = 26 against the oracle,
+and n = 27..34 (too large for the oracle's host memory budget) through
+properties that hold at any size: beta = 0 leaves the distribution uniform so
+<C> = (1'Q1 + tr Q)/4, unit norm, the p = 1 closed form, and the diagonal-Q
+product formula; the largest states (n = 34 complex64, n = 33 complex128,
+128 GiB each) against the p = 1 closed form.
+
+Dense couplings in the middle passes of these plans are pinned by a
+reduction: with gamma_1 = 0 the first layer's phase is the identity and its
+mixer e^{i beta_1 sum X} only multiplies |+> by a global phase, so a p = 2
+state is the p = 1 state of (gamma_2, beta_2), and with gamma_1 = gamma_2 = 0
+a p = 3 state the p = 1 state of (gamma_3, beta_3).  The passes still run
+every layer on the dense Q.  For the gradient, d<C>/dbeta_1 = 0 and
+(d<C>/dgamma_2, d<C>/dbeta_2) are the derivatives of the p = 1 closed form."""
 import numpy as np
 import pytest
 
@@ -23,39 +31,48 @@ def api():
     return a
 
 
+@pytest.fixture(scope="module")
+def ctx(api):
+    """A context of its own: its scratch (up to 160 GiB here) is released
+    when the module ends, before other tests size their buffers."""
+    c = api.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
 def cuda(x):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda:0")
 
 
-def test_precision_n24_all_sets(api):
+def test_precision_n24_all_sets(api, ctx):
     W = workloads.WORKLOADS["precision_n24"]
     n, p, S = W["n"], W["p"], W["sets"]
     Q = workloads.qubo(n, W["q_seed"])
     g, b = workloads.params(S, p, W["p_seed"])
     print("n=24 c64/c128 16 sets", flush=True)
-    e64 = api.expect(cuda(Q), cuda(g), cuda(b), prec="c64").cpu().numpy()[0]
-    e128 = api.expect(cuda(Q), cuda(g), cuda(b), prec="c128").cpu().numpy()[0]
+    e64 = api.expect(cuda(Q), cuda(g), cuda(b), prec="c64", ctx=ctx).cpu().numpy()[0]
+    e128 = api.expect(cuda(Q), cuda(g), cuda(b), prec="c128", ctx=ctx).cpu().numpy()[0]
     cm = float(np.max(np.abs(oracle.cost_table(Q))))
-    sel = [0, S - 1]
-    eo, _, _ = oracle.expect(Q, g[sel], b[sel])
-    for i, s in enumerate(sel):
-        assert abs(e128[s] - eo[i]) <= 1e-10 * max(1.0, abs(eo[i]))
-        assert abs(e64[s] - eo[i]) <= 1e-5 * cm
+    eo, _, _ = oracle.expect(Q, g, b)  # all 16 sets
+    for s in range(S):
+        assert abs(e128[s] - eo[s]) <= 1e-10 * max(1.0, abs(eo[s])), s
+        assert abs(e64[s] - eo[s]) <= 1e-5 * cm, s
     assert np.max(np.abs(e64 - e128)) <= 1e-5 * cm
-    psi, _, nr = api.state(cuda(Q), cuda(g[:1]), cuda(b[:1]), prec="c64")
+    psi, _, nr = api.state(cuda(Q), cuda(g[:1]), cuda(b[:1]), prec="c64", ctx=ctx)
     ref = oracle.state(Q, g[0], b[0])
     l2 = np.linalg.norm(psi.cpu().numpy()[0, 0].astype(np.complex128) - ref)
     assert l2 <= 1e-4, l2
     assert abs(nr.item() - 1.0) <= 1e-5
 
 
-def test_n26_against_oracle(api):
+def test_n26_against_oracle(api, ctx):
     n, p = 26, 2
     Q = workloads.qubo(n, 26)
     g, b = workloads.params(1, p, 27)
     print("n=26", flush=True)
-    e64 = api.expect(cuda(Q), cuda(g), cuda(b), prec="c64").cpu().numpy()[0]
-    e128 = api.expect(cuda(Q), cuda(g), cuda(b), prec="c128").cpu().numpy()[0]
+    e64 = api.expect(cuda(Q), cuda(g), cuda(b), prec="c64", ctx=ctx).cpu().numpy()[0]
+    e128 = api.expect(cuda(Q), cuda(g), cuda(b), prec="c128", ctx=ctx).cpu().numpy()[0]
     eo, _, _ = oracle.expect(Q, g, b)
     cm = float(np.max(np.abs(oracle.cost_table(Q))))
     assert abs(e128[0] - eo[0]) <= 1e-10 * max(1.0, abs(eo[0]))
@@ -70,73 +87,73 @@ def _cmax_bound(Q):
     return float(np.abs(Q).sum())
 
 
-def test_n32_beta_zero_uniform_mean_and_norm(api):
+def test_n32_beta_zero_uniform_mean_and_norm(api, ctx):
     Q = workloads.qubo(N32, 6)
     g, b = workloads.params(2, 2, 16)
     b[:] = 0.0
     print("n=32 beta=0", flush=True)
-    e, nr = api.expect(cuda(Q), cuda(g), cuda(b), prec="c64", norm=True)
+    e, nr = api.expect(cuda(Q), cuda(g), cuda(b), prec="c64", ctx=ctx, norm=True)
     e, nr = e.cpu().numpy()[0], nr.cpu().numpy()[0]
     mean = dense_ref.mean_cost(Q)
     assert np.all(np.abs(nr - 1.0) <= 1e-5), nr
     assert np.all(np.abs(e - mean) <= 1e-5 * _cmax_bound(Q)), (e, mean)
 
 
-def test_n32_p1_closed_form(api):
+def test_n32_p1_closed_form(api, ctx):
     Q = workloads.qubo(N32, 6)
     g, b = workloads.params(2, 1, 17)
     print("n=32 p=1 closed form", flush=True)
-    e = api.expect(cuda(Q), cuda(g), cuda(b), prec="c64").cpu().numpy()[0]
+    e = api.expect(cuda(Q), cuda(g), cuda(b), prec="c64", ctx=ctx).cpu().numpy()[0]
     for s in range(2):
         cf = dense_ref.p1_closed_form(Q, g[s, 0], b[s, 0])
         assert abs(e[s] - cf) <= 1e-5 * _cmax_bound(Q), (s, e[s], cf)
 
 
-def test_n32_diagonal_q_product_formula(api):
+def test_n32_diagonal_q_product_formula(api, ctx):
     rng = np.random.default_rng(32)
     d = rng.uniform(-1, 1, N32)
     Q = np.diag(d)
     g, b = workloads.params(1, 2, 18)
     print("n=32 diagonal", flush=True)
-    e = api.expect(cuda(Q), cuda(g), cuda(b), prec="c64").cpu().numpy()[0]
+    e = api.expect(cuda(Q), cuda(g), cuda(b), prec="c64", ctx=ctx).cpu().numpy()[0]
     ref = dense_ref.diagonal_expect(d, g[0], b[0])
     assert abs(e[0] - ref) <= 1e-5 * np.abs(d).sum(), (e[0], ref)
 
 
 @pytest.mark.parametrize("n", [27, 28, 30])
-def test_three_sets_p1_closed_form(api, n):
+def test_three_sets_p1_closed_form(api, ctx, n):
     """Three-set complex64 plans whose kind-2 sets keep 6 to 8 contiguous low
     qubits (512-byte to 2 KiB runs): first, lead-only and last passes."""
     Q = workloads.qubo(n, 60 + n)
     g, b = workloads.params(2, 1, 70 + n)
     print(f"n={n} p=1 closed form", flush=True)
-    e = api.expect(cuda(Q), cuda(g), cuda(b), prec="c64").cpu().numpy()[0]
+    e = api.expect(cuda(Q), cuda(g), cuda(b), prec="c64", ctx=ctx).cpu().numpy()[0]
     for s in range(2):
         cf = dense_ref.p1_closed_form(Q, g[s, 0], b[s, 0])
         assert abs(e[s] - cf) <= 1e-5 * _cmax_bound(Q), (s, e[s], cf)
 
 
 @pytest.mark.parametrize("n", [28, 30])
-def test_three_sets_diagonal_q_p3(api, n):
+def test_three_sets_diagonal_q_p3(api, ctx, n):
     """The same plans at p = 3 (middle passes on the kind-2 sets)."""
     rng = np.random.default_rng(n)
     d = rng.uniform(-1, 1, n)
     g, b = workloads.params(1, 3, 80 + n)
     print(f"n={n} diagonal p=3", flush=True)
-    e = api.expect(cuda(np.diag(d)), cuda(g), cuda(b), prec="c64").cpu().numpy()[0]
+    e = api.expect(cuda(np.diag(d)), cuda(g), cuda(b), prec="c64", ctx=ctx).cpu().numpy()[0]
     ref = dense_ref.diagonal_expect(d, g[0], b[0])
     assert abs(e[0] - ref) <= 1e-5 * np.abs(d).sum(), (e[0], ref)
 
 
 @pytest.mark.parametrize("prec,n", [("c64", 34), ("c128", 33)])
-def test_max_size_p1_closed_form(api, prec, n):
+def test_max_size_p1_closed_form(api, ctx, prec, n):
     """The largest states: n = QAOA_MAX_N = 34 in complex64 (a 128 GiB state;
     sets of 14, 10 and 10 qubits, the kind-2 tiles on 128-byte runs) and
     n = 33 in complex128 (128 GiB; 64-byte runs)."""
     Q = workloads.qubo(n, 90 + n)
     g, b = workloads.params(1, 1, 95 + n)
     print(f"n={n} {prec} p=1 closed form", flush=True)
-    e, nr = api.expect(cuda(Q), cuda(g), cuda(b), prec=prec, norm=True)
+    e, nr = api.expect(cuda(Q), cuda(g), cuda(b), prec=prec, ctx=ctx, norm=True)
     e, nr = float(e.cpu().numpy()[0][0]), float(nr.cpu().numpy()[0][0])
     cf = dense_ref.p1_closed_form(Q, g[0, 0], b[0, 0])
     bound = _cmax_bound(Q)
@@ -145,14 +162,64 @@ def test_max_size_p1_closed_form(api, prec, n):
     assert abs(nr - 1.0) <= (1e-5 if prec == "c64" else 1e-12), nr
 
 
-def test_large_n32_four_sets_runs_and_is_normalised(api):
+def test_large_n32_four_sets_runs_and_is_normalised(api, ctx):
     """The n = 32, p = 2, 4-set workload: every set keeps unit norm and the
     four <C> lie within [min C, max C] bounds."""
     W = workloads.WORKLOADS["large_n32"]
     Q = workloads.qubo(W["n"], W["q_seed"])
     g, b = workloads.params(W["sets"], W["p"], W["p_seed"])
     print("n=32 workload", flush=True)
-    e, nr = api.expect(cuda(Q), cuda(g), cuda(b), prec="c64", norm=True)
+    e, nr = api.expect(cuda(Q), cuda(g), cuda(b), prec="c64", ctx=ctx, norm=True)
     e, nr = e.cpu().numpy()[0], nr.cpu().numpy()[0]
     assert np.all(np.abs(nr - 1.0) <= 1e-5)
     assert np.all(np.abs(e) <= _cmax_bound(Q))
+
+
+@pytest.mark.parametrize("prec,n,p", [("c64", 27, 2), ("c64", 29, 3), ("c64", 31, 2),
+                                      ("c64", 32, 3), ("c64", 33, 2), ("c64", 34, 2),
+                                      ("c128", 27, 2), ("c128", 30, 3), ("c128", 33, 2)])
+def test_leading_zero_gammas_reduce_to_p1(api, ctx, prec, n, p):
+    """Every pass of the multi-set plans on a dense Q: the first p - 1 layers
+    have gamma = 0, so <C> equals the p = 1 closed form of the last layer."""
+    S = 2 if n <= 32 else 1  # 128 GiB states above n = 32
+    Q = workloads.qubo(n, 110 + n)
+    g, b = workloads.params(S, p, 120 + n + p)
+    g[:, :p - 1] = 0.0
+    print(f"n={n} {prec} p={p} leading gamma = 0", flush=True)
+    e, nr = api.expect(cuda(Q), cuda(g), cuda(b), prec=prec, ctx=ctx, norm=True)
+    e, nr = e.cpu().numpy()[0], nr.cpu().numpy()[0]
+    bound = _cmax_bound(Q)
+    tol = 1e-5 * bound if prec == "c64" else 1e-10 * max(1.0, bound)
+    for s in range(S):
+        cf = dense_ref.p1_closed_form(Q, g[s, p - 1], b[s, p - 1])
+        assert abs(e[s] - cf) <= tol, (s, e[s], cf)
+        assert abs(nr[s] - 1.0) <= (1e-5 if prec == "c64" else 1e-12), nr[s]
+
+
+@pytest.mark.parametrize("prec,n", [("c64", 28), ("c64", 30), ("c64", 32), ("c128", 28),
+                                    ("c128", 30)])
+def test_grad_gamma1_zero_reduces_to_p1(api, ctx, prec, n):
+    """The checkpointed adjoint at n = 28..32 (up to 160 GiB of checkpoints):
+    with gamma_1 = 0 and p = 2, <C> and (d<C>/dgamma_2, d<C>/dbeta_2) are the
+    p = 1 closed form and its central differences (h = 1e-5) at
+    (gamma_2, beta_2), and d<C>/dbeta_1 = 0."""
+    p = 2
+    Q = workloads.qubo(n, 130 + n)
+    g, b = workloads.params(1, p, 140 + n)
+    g[:, 0] = 0.0
+    print(f"grad n={n} {prec} gamma_1 = 0", flush=True)
+    e, dg, db = (x.cpu().numpy()[0, 0] for x in api.grad(cuda(Q), cuda(g), cuda(b), prec=prec, ctx=ctx))
+    g2, b2 = g[0, 1], b[0, 1]
+    cf = dense_ref.p1_closed_form(Q, g2, b2)
+    h = 1e-5
+    fdg = (dense_ref.p1_closed_form(Q, g2 + h, b2) - dense_ref.p1_closed_form(Q, g2 - h, b2)) / (2 * h)
+    fdb = (dense_ref.p1_closed_form(Q, g2, b2 + h) - dense_ref.p1_closed_form(Q, g2, b2 - h)) / (2 * h)
+    bound = _cmax_bound(Q)
+    # central differences of an O(n^2) function in FP64: truncation h^2 and
+    # rounding ~1e-16 * bound / h, both far below the state tolerances
+    tol = 1e-5 * bound * p if prec == "c64" else 1e-7 * max(1.0, bound)
+    etol = 1e-5 * bound if prec == "c64" else 1e-10 * max(1.0, bound)
+    assert abs(e - cf) <= etol, (e, cf)
+    assert abs(dg[1] - fdg) <= tol, (dg[1], fdg)
+    assert abs(db[1] - fdb) <= tol, (db[1], fdb)
+    assert abs(db[0]) <= tol, db[0]
