@@ -5,8 +5,8 @@
 // FP64 arithmetic throughout: 256 threads x 32 double2 amplitudes (5 register
 // bits, 6 lane bits, 2 wave bits), the same 128 VGPRs of tile as the
 // complex64 pass.  The phase factors come from sincospi in FP64, so no FP32
-// rounding enters the state (the complex128 tolerance of Sec. III is 1e-10
-// relative on <C>).
+// rounding enters the state (this library's complex128 accuracy target is
+// 1e-10 relative on <C>; the paper states no tolerance).
 //
 // The other sets keep only 2 contiguous low tile bits (64 B runs of a
 // complex128 state), so their tile mixes up to 11 qubits and n <= 24 needs
