@@ -98,6 +98,25 @@ int qaoa_expect(qaoa_ctx* ctx, int prec, int B, int n, int p, int S,
                 double* expect, double* norm, void* probs,
                 qaoa_stream_t stream);
 
+/* qaoa_expect for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results and errors as qaoa_expect, but the working memory
+ * (state vectors, per-state pass tables, partial sums) comes from a fixed
+ * device array of QAOA_NOALLOC_SCRATCH_BYTES that every GPU the library runs
+ * on holds from qaoa_create until the process ends; the call itself makes no
+ * hipMalloc, hipFree or other allocation and records no event.  Every call on
+ * one GPU shares that array and leaves its contents behind (no call relies on
+ * them: each writes every scratch word before reading it), so calls whose
+ * work overlaps on one GPU race: issue them on one stream, or order them.
+ * Errors as qaoa_expect; QAOA_ERR_OUT_OF_MEMORY when the B*S states, their
+ * tables and partial sums exceed the array (e.g. one n = 24 or 16 n = 20
+ * complex64 states fit). */
+#define QAOA_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int qaoa_expect_noalloc(qaoa_ctx* ctx, int prec, int B, int n, int p, int S,
+                        const double* Q, const double* gammas, const double* betas,
+                        double* expect, double* norm, void* probs,
+                        qaoa_stream_t stream);
+
 /* The Eq. (2) state itself, psi [B][S][2^n] of interleaved (re, im) pairs:
  * FP64 pairs for C128, FP32 pairs for C64 (the library's state as computed).
  * expect/norm as in qaoa_expect (nullable).  Errors as qaoa_expect. */

@@ -37,7 +37,7 @@ ERROR_NAMES = {
 # Every symbol include/dqaoa.h declares.
 EXPORTS = [
     "qaoa_last_error", "qaoa_version", "qaoa_create", "qaoa_destroy",
-    "qaoa_expect", "qaoa_state", "qaoa_sample", "qaoa_grad", "qaoa_plan", "qaoa_plan_passes",
+    "qaoa_expect", "qaoa_expect_noalloc", "qaoa_state", "qaoa_sample", "qaoa_grad", "qaoa_plan", "qaoa_plan_passes",
     "qaoa_profile_enable", "qaoa_profile_read", "qaoa_queue_create",
     "qaoa_queue_destroy", "qaoa_submit", "qaoa_poll", "qaoa_wait",
     "qaoa_cancel", "qaoa_queue_get_stats",
@@ -126,6 +126,7 @@ def load():
     L.qaoa_create.argtypes = [ctypes.POINTER(vp), i, sz]
     L.qaoa_destroy.argtypes = [vp]
     L.qaoa_expect.argtypes = [vp, i, i, i, i, i, dp, dp, dp, dp, dp, dp, vp]
+    L.qaoa_expect_noalloc.argtypes = [vp, i, i, i, i, i, dp, dp, dp, dp, dp, dp, vp]
     L.qaoa_state.argtypes = [vp, i, i, i, i, i, dp, dp, dp, dp, dp, dp, vp]
     L.qaoa_sample.argtypes = [vp, i, i, i, i, dp, dp, dp, i, u64, dp, dp, dp,
                               dp, dp, vp]

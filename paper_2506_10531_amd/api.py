@@ -148,6 +148,30 @@ def expect(Q, gammas, betas, prec="c64", probs=False, norm=False, ctx=None):
     return out[0] if len(out) == 1 else tuple(out)
 
 
+def expect_noalloc(Q, gammas, betas, out, norm=None, probs=None, prec="c64", ctx=None):
+    """qaoa_expect_noalloc: <C> into the caller's ``out`` [B, S] (and norms
+    [B, S], |psi|^2 [B, S, 2^n] if given) with no device allocation by the
+    library: its working memory is the library's fixed per-GPU scratch."""
+    Q = _dev(Q, "Q")
+    gammas = _dev(gammas, "gammas")
+    betas = _dev(betas, "betas")
+    Q, g, b, B, n, S, p = _shape_qp(Q, gammas, betas)
+    pc = _prec(prec)
+    for t, name in ((out, "out"), (norm, "norm")):
+        if t is not None and (t.dtype != torch.float64 or not t.is_cuda or t.numel() != B * S
+                              or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous GPU float64 tensor of {B * S}")
+    if probs is not None:
+        dt = torch.float64 if pc == _lib.QAOA_C128 else torch.float32
+        if probs.dtype != dt or not probs.is_cuda or probs.numel() != B * S << n or \
+                not probs.is_contiguous():
+            raise ValueError(f"probs must be a contiguous GPU {dt} tensor of {B * S << n}")
+    ctx = ctx or default_context(Q.device.index)
+    _lib.check(_lib.load().qaoa_expect_noalloc(ctx.h, pc, B, n, p, S, _ptr(Q), _ptr(g), _ptr(b),
+                                               _ptr(out), _ptr(norm), _ptr(probs), _stream()))
+    return out
+
+
 def state(Q, gammas, betas, prec="c64", ctx=None):
     """(psi [B, S, 2^n] complex128/complex64, <C> [B, S], norm [B, S])."""
     Q = _dev(Q, "Q")

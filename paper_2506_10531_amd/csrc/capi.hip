@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 namespace dq {
@@ -650,6 +651,31 @@ struct qaoa_ctx : public PassTimer {
 
 namespace {
 
+// Device scratch of qaoa_expect_noalloc: a file-scope array each GPU holds
+// from the library's first use on it until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol); qaoa_create takes its device address once per
+// device and the entry point uses that address.
+constexpr size_t NOALLOC_BYTES = QAOA_NOALLOC_SCRATCH_BYTES;
+constexpr int NOALLOC_DEVICES = 64;
+__device__ __align__(256) char scratch[NOALLOC_BYTES];
+std::mutex g_noalloc_mu;
+char* g_noalloc_ptr[NOALLOC_DEVICES] = {};
+
+// With `device` current: the device address of `scratch` on it.
+int noalloc_setup(int device) {
+  if (device < 0 || device >= NOALLOC_DEVICES)
+    return set_error(QAOA_ERR_UNSUPPORTED, "device %d beyond the %d the library tracks", device,
+                     NOALLOC_DEVICES);
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (g_noalloc_ptr[device]) return QAOA_OK;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_error(e, "hipGetSymbolAddress(scratch)");
+  g_noalloc_ptr[device] = static_cast<char*>(ptr);
+  return QAOA_OK;
+}
+
 struct DeviceGuard {
   int prev = -1;
   bool ok = true;
@@ -772,6 +798,12 @@ int qaoa_create(qaoa_ctx** out, int device, size_t hbm_budget) {
   if (e != hipSuccess) {
     delete c;
     return hip_error(e, "hipEventCreate");
+  }
+  int rc = noalloc_setup(device);
+  if (rc) {
+    (void)hipEventDestroy(c->done);
+    delete c;
+    return rc;
   }
   *out = c;
   return QAOA_OK;
@@ -896,6 +928,32 @@ int qaoa_expect(qaoa_ctx* ctx, int prec, int B, int n, int p, int S,
                       ctx->timer());
   if (rc) return rc;
   return finish(ctx, s);
+}
+
+int qaoa_expect_noalloc(qaoa_ctx* ctx, int prec, int B, int n, int p, int S,
+                        const double* Q, const double* gammas, const double* betas,
+                        double* expect, double* norm, void* probs, qaoa_stream_t stream) {
+  int rc = check_common(ctx, prec, B, n, p, S);
+  if (rc) return rc;
+  if (!Q || !gammas || !betas || !expect)
+    return set_error(QAOA_ERR_INVALID_ARG, "Q, gammas, betas and expect must be non-NULL");
+  Layout L;
+  rc = make_layout(OP_EXPECT, prec, B, n, p, S, 0, &L);
+  if (rc) return rc;
+  if (L.cv.total > NOALLOC_BYTES)
+    return set_error(QAOA_ERR_OUT_OF_MEMORY,
+                     "qaoa_expect_noalloc: %d state(s) of %d qubits need %zu bytes of scratch; "
+                     "its fixed scratch holds %zu",
+                     B * S, n, L.cv.total, NOALLOC_BYTES);
+  if (ctx->device < 0) return set_error(QAOA_ERR_NO_DEVICE, "host-only context");
+  char* base = g_noalloc_ptr[ctx->device];  // set by qaoa_create on this device
+  if (!base) return set_error(QAOA_ERR_HIP, "no scratch address for device %d", ctx->device);
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  rc = enqueue_expect(L, base, Q, gammas, betas, expect, norm, probs, nullptr, s, nullptr);
+  if (rc) return rc;
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? QAOA_OK : hip_error(e, "kernel launch");
 }
 
 int qaoa_state(qaoa_ctx* ctx, int prec, int B, int n, int p, int S,

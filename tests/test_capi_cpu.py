@@ -60,6 +60,22 @@ def test_invalid_arguments_rejected_before_device_work(hctx, kw):
     assert _lib.load().qaoa_last_error() != b""
 
 
+def test_noalloc_validates_and_bounds_its_scratch(hctx):
+    L = _lib.load()
+    P = lambda x: ctypes.c_void_p(0x1000) if x else None  # never dereferenced
+
+    def call(prec=1, B=1, n=10, p=2, S=1, e=1):
+        return L.qaoa_expect_noalloc(hctx, prec, B, n, p, S, P(1), P(1), P(1), P(e), None,
+                                     None, None)
+    assert call() == _lib.ERR_NO_DEVICE
+    assert call(n=24) == _lib.ERR_NO_DEVICE           # one 128 MiB state fits
+    assert call(n=26) == _lib.ERR_OUT_OF_MEMORY       # 512 MiB does not
+    assert b"fixed scratch" in L.qaoa_last_error()
+    assert call(n=20, S=40) == _lib.ERR_OUT_OF_MEMORY  # 320 MiB of states
+    for kw in (dict(prec=2), dict(B=0), dict(n=35), dict(p=0), dict(e=0)):
+        assert call(**kw) == _lib.ERR_INVALID_ARG, kw
+
+
 def test_null_context_rejected():
     assert _expect(None) == _lib.ERR_INVALID_ARG
 
