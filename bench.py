@@ -65,6 +65,44 @@ def load_traffic(prec: str = "c64"):
     return rec.get("bytes_per_launch")
 
 
+def timed_repeats(fn, min_s: float = 1.0, min_reps: int = 10) -> dict:
+    """The timing protocol: calls of fn (each followed by a device
+    synchronisation) until at least min_reps calls and min_s seconds have
+    been timed; median and minimum per call."""
+    import numpy as np
+    import torch
+    ts = []
+    while len(ts) < min_reps or sum(ts) < min_s:
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return {"median_ms": 1e3 * float(np.median(ts)), "min_ms": 1e3 * float(np.min(ts)),
+            "repeats": len(ts), "timed_s": float(sum(ts))}
+
+
+def host_cpu() -> dict:
+    """The host the CPU oracle runs on: model name and usable cores."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "usable_cores": len(os.sched_getaffinity(0))}
+
+
+PAPER_CONTEXT = {
+    "gpu_over_cpu": "up to 10x",
+    "hardware": "Frontier: AMD Instinct MI250X GPUs against 64-core AMD EPYC CPUs",
+    "workload": "DQAOA on dense QUBOs of N = 300/500/1000 split into sub-QUBOs of 20 "
+                "variables, p = 1, COBYLA",
+    "note": "context only: other hardware, simulators and workload; not a target",
+}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,7 +114,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the complex128 comparison and error report")
-    ap.add_argument("--serving-requests", type=int, default=1024,
+    ap.add_argument("--serving-requests", type=int, default=4096,
                     help="requests replayed against the batched solve queue (0: skip)")
     ap.add_argument("--serving-single", type=int, default=-1,
                     help="requests of the same trace replayed against the one-at-a-time "
@@ -93,7 +131,7 @@ def parse():
     ap.add_argument("--grad-steps", type=int, default=5,
                     help="gradient calls per precision on the 512 x n=16, p=6 "
                          "differentiation workload (0: skip)")
-    ap.add_argument("--legs", default="serving,large,dqaoa,cobyla,maxcut,grad",
+    ap.add_argument("--legs", default="plain,p1,serving,large,dqaoa,cobyla,maxcut,grad",
                     help="comma-separated legs to run after the main workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a 2 GiB device copy (counter calibration)")
@@ -118,7 +156,8 @@ def copy_probe():
                       "copy_GBps": 2 * a.numel() * 8 / (ms * 1e-3) / 1e9}))
 
 
-def serving_leg(requests: int, one_at_a_time: int, max_slots: int, calib: int):
+def serving_leg(requests: int, one_at_a_time: int, max_slots: int, calib: int,
+                no_cpu: bool = False):
     """Sub-QUBO solves/s and p50/p99 latency of the solve queue.
 
     Requests come from one dense N = 1000 QUBO by random decomposition
@@ -172,6 +211,7 @@ def serving_leg(requests: int, one_at_a_time: int, max_slots: int, calib: int):
                     solves_per_s=len(ok) / span, p50_ms=float(np.percentile(lat, 50)),
                     p99_ms=float(np.percentile(lat, 99)), span_s=span)
 
+    ns = [Q.shape[0] for Q, _, _, _ in items]
     cal = run(True, items[:calib], None)
     rate = 0.8 * cal["solves_per_s"]
     arr = workloads.poisson_arrivals(requests, rate, W["arrival_seed"])
@@ -179,7 +219,7 @@ def serving_leg(requests: int, one_at_a_time: int, max_slots: int, calib: int):
     if one_at_a_time < 0 or one_at_a_time > requests:
         one_at_a_time = requests
     single = run(False, items[:one_at_a_time], arr[:one_at_a_time])
-    return {
+    out = {
         "workload": (f"{requests} sub-QUBOs of one dense N={W['N']} QUBO, n~U{{"
                      f"{W['n_lo']}..{W['n_hi']}}}, p={p}, {evals} Adam evaluations + "
                      f"{shots} shots each, complex64, Poisson arrivals at 0.8 x the "
@@ -192,9 +232,126 @@ def serving_leg(requests: int, one_at_a_time: int, max_slots: int, calib: int):
                                     else "first requests of the same trace")),
         "max_slots": max_slots,
     }
+    if not no_cpu:
+        out["cpu_oracle"] = serving_oracle(W["n_lo"], W["n_hi"], p, evals, shots, ns, 5000)
+    return out
 
 
-def large_state_leg(steps: int):
+def plain_leg(no_cpu: bool):
+    """The plain form: one dense n = 10 QUBO, p = 2, 64 parameter sets,
+    complex128, <C> and the full probability vector of every set (one
+    qaoa_expect per call).  Small enough that every state lives in one LDS
+    tile: the call is bound by FP64 VALU work and launch latency, not HBM, so
+    it reports updates/s and the FP64 rate of the counted arithmetic (6n
+    flops of mixer butterflies and 6 of the phase multiply per
+    amplitude-layer) against MI355X's 78.6 TFLOP/s FP64 vector peak."""
+    import numpy as np
+    import torch
+
+    from paper_2506_10531_amd import api, workloads
+
+    W = workloads.WORKLOADS["plain_n10"]
+    n, p, S = W["n"], W["p"], W["sets"]
+    Qh = workloads.qubo(n, W["q_seed"])
+    g, b = workloads.params(S, p, W["p_seed"])
+    dev = torch.device("cuda:0")
+    Q, gd, bd = (torch.as_tensor(x, device=dev) for x in (Qh, g, b))
+    ctx = api.Context(0)
+
+    def call():
+        api.expect(Q, gd, bd, prec="c128", probs=True, ctx=ctx)
+    for _ in range(5):
+        call()
+    tp = timed_repeats(call)
+    ctx.close()
+    updates = S * p * (1 << n)
+    flops = updates * (6 * n + 6)
+    out = {"workload": "plain_n10: one dense n=10 QUBO, p=2, 64 parameter sets, complex128, "
+                       "<C> and probabilities",
+           "value": updates / (tp["median_ms"] * 1e-3), "unit": "amplitude-layer updates/s",
+           "timing": tp,
+           "fp64_counted_flops_per_call": flops,
+           "fp64_TFLOPs": flops / (tp["median_ms"] * 1e-3) / 1e12,
+           "fp64_valu_frac": flops / (tp["median_ms"] * 1e-3) / 78.6e12}
+    if not no_cpu:
+        import oracle
+        tc, calls = 0.0, 0
+        while tc < 2.0 or calls < 3:
+            t0 = time.perf_counter()
+            oracle.expect(Qh, g, b, probs=True)
+            tc += time.perf_counter() - t0
+            calls += 1
+        out["cpu_oracle"] = {"value": calls * updates / tc, "unit": "amplitude-layer updates/s",
+                             "cores": oracle.num_threads(), "kind": "oracle",
+                             "sample": f"{calls} whole calls (64 sets with probabilities)"}
+    return out
+
+
+def p1_leg():
+    """The paper's depth: the n = 24 workload at p = 1 (16 sets, complex64),
+    i.e. a first pass (generate |+>, phase, lead half-mixer, store) and a last
+    pass (load, trail half-mixer, <C>) per evaluation, with their achieved
+    bandwidth from the library's per-launch events."""
+    import torch
+
+    from paper_2506_10531_amd import api, workloads
+
+    W = workloads.WORKLOADS["precision_n24"]
+    n, S = W["n"], W["sets"]
+    Q = torch.as_tensor(workloads.qubo(n, W["q_seed"]), device="cuda:0")
+    g, b = workloads.params(S, 1, W["p_seed"])
+    gd, bd = (torch.as_tensor(x, device="cuda:0") for x in (g, b))
+    ctx = api.Context(0)
+
+    def call():
+        api.expect(Q, gd, bd, prec="c64", ctx=ctx)
+    for _ in range(3):
+        call()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    tp = timed_repeats(call)
+    ctx.profile(False)
+    launches, pass_ms, pass_bytes = ctx.profile_read(reset=True)
+    ctx.close()
+    achieved = pass_bytes / (pass_ms * 1e-3) / 1e9
+    return {"workload": "p1_n24: the n=24 QUBO of the main workload at p=1, 16 sets, complex64",
+            "value": S * (1 << n) / (tp["median_ms"] * 1e-3), "unit": "amplitude-layer updates/s",
+            "timing": tp, "pass_launches": launches, "achieved_GBps": achieved,
+            "frac": achieved / PEAK_HBM_GBPS}
+
+
+def serving_oracle(n_lo: int, n_hi: int, p: int, evals: int, shots: int, ns, seed: int) -> dict:
+    """The oracle's one-request-at-a-time solve rate on the serving workload,
+    extrapolated: one evaluation (exact <C> and adjoint gradient in
+    complex128) is timed per qubit count, then a solve of n qubits costs
+    `evals` evaluations plus a sampling pass, averaged over the trace's mix
+    of n (a whole solve at n = 22 takes about a minute on the host)."""
+    import numpy as np
+
+    import oracle
+    from paper_2506_10531_amd import workloads
+
+    per_n = {}
+    for n in range(n_lo, n_hi + 1):
+        Q = workloads.qubo(n, seed + n)
+        g, b = workloads.params(1, p, seed + 100 + n)
+        t0 = time.perf_counter()
+        oracle.grad(Q, g, b)
+        t1 = time.perf_counter()
+        oracle.sample(Q, g[0], b[0], shots, 1)
+        t2 = time.perf_counter()
+        per_n[n] = evals * (t1 - t0) + (t2 - t1)
+    mean = float(np.mean([per_n[int(n)] for n in ns]))
+    return {"solves_per_s": 1.0 / mean, "extrapolated": True, "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"one timed complex128 evaluation (<C> + adjoint gradient) and one "
+                      f"{shots}-shot sampling per n = {n_lo}..{n_hi}, scaled to {evals} "
+                      f"evaluations per solve and averaged over the trace's n",
+            "seconds_per_solve_by_n": {str(k): v for k, v in per_n.items()}}
+
+
+def large_state_leg(steps: int, no_cpu: bool = False):
     """The n = 32, p = 2, 4-set complex64 workload (4 x 32 GiB states): one
     qaoa_expect per step, timed like the main workload, with the register-tile
     passes' achieved bandwidth from the library's per-launch events."""
@@ -223,9 +380,23 @@ def large_state_leg(steps: int):
     launches, pass_ms, pass_bytes = ctx.profile_read(reset=True)
     en = e.cpu().numpy()[0]
     del e
+    tp = timed_repeats(lambda: api.expect(Q, gd, bd, prec="c64", ctx=ctx), min_s=1.0,
+                       min_reps=10)
     ctx.close()
     achieved = (pass_bytes / launches) / (pass_ms / launches * 1e-3) / 1e9
     floor = S * p * (1 << n) * 16
+    cpu = None
+    if not no_cpu:
+        import oracle
+        nc = 26  # the largest state the oracle takes on the host here (1 GiB complex128)
+        Qc = workloads.qubo(nc, W["q_seed"])
+        t0 = time.perf_counter()
+        oracle.expect(Qc, g[:1], b[:1])
+        tc = time.perf_counter() - t0
+        cpu = {"value": p * (1 << nc) / tc, "unit": "amplitude-layer updates/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"one n={nc}, p={p} state (cost table + {p} layers), {tc:.1f} s; "
+                         f"n=32 (64 GiB in complex128) is not run on the host"}
     return {
         "workload": "large_n32: one dense n=32 QUBO, p=2, 4 parameter sets, complex64 "
                     "(4 x 32 GiB states)",
@@ -240,10 +411,12 @@ def large_state_leg(steps: int):
         "achieved_GBps": achieved,
         "frac": achieved / PEAK_HBM_GBPS,
         "expect": [float(x) for x in en],
+        "timing": tp,
+        "cpu_oracle": cpu,
     }
 
 
-def grad_leg(steps: int):
+def grad_leg(steps: int, no_cpu: bool = False):
     """The differentiation workload (512 dense n = 16 QUBOs, p = 6): qaoa_grad
     in each precision, timed over `steps` calls, with the adjoint and
     checkpoint passes' bandwidth from the library's per-launch events."""
@@ -285,8 +458,21 @@ def grad_leg(steps: int):
             "achieved_GBps": achieved,
             "frac": achieved / PEAK_HBM_GBPS,
             "tile_qubits": plan["tile_qubits"],
+            "timing": timed_repeats(lambda: api.grad(Q, gd, bd, prec=prec, ctx=ctx)),
         }
     ctx.close()
+    if not no_cpu:
+        import oracle
+        Qh = workloads.qubos(B, n, W["q_seed"])
+        k = 16
+        t0 = time.perf_counter()
+        for i in range(k):
+            oracle.grad(Qh[i], g[i:i + 1], b[i:i + 1])
+        tc = time.perf_counter() - t0
+        res["cpu_oracle"] = {"grads_per_s": k / tc, "extrapolated": True,
+                             "cores": oracle.num_threads(), "kind": "oracle",
+                             "sample": f"complex128 adjoint gradients of the first {k} of the "
+                                       f"{B} problems, {tc:.1f} s"}
     return res
 
 
@@ -483,6 +669,8 @@ def main():
     launches, pass_ms, pass_bytes = ctx.profile_read(reset=True)
     ev_ms = ev0.elapsed_time(ev1)
 
+    # the timing protocol beside the contract's K steps: >= 10 calls and >= 1 s
+    timing = timed_repeats(lambda: api.expect(Qd, gd, bd, prec=prec, ctx=ctx))
     ms_per_step = 1e3 * wall / args.steps
     value = updates_per_step * args.steps / wall
     avg_launch_ms = pass_ms / max(launches, 1)
@@ -510,6 +698,9 @@ def main():
                    "prec": prec, "q_seed": W["q_seed"], "p_seed": W["p_seed"]},
         "hbm_GBps": floor_bytes_per_step * args.steps / wall / 1e9,
         "event_ms_per_step": ev_ms / args.steps,
+        "timing": timing,
+        "host_cpu": host_cpu(),
+        "paper_context": PAPER_CONTEXT,
         "plan": {"passes": plan["passes"], "sets": plan["sets"],
                  "tile_qubits": plan["tile_qubits"],
                  "state_reads": plan["state_reads"],
@@ -594,12 +785,17 @@ def main():
             out["errors"]["c128_vs_oracle_expect_max_rel"] = float(
                 np.max(np.abs(ec[:k] - eo) / np.maximum(np.abs(eo), 1.0)))
     legs = set(x for x in args.legs.split(",") if x)
+    if "plain" in legs:
+        out["plain"] = plain_leg(args.no_cpu_baseline)
+    if "p1" in legs:
+        out["p1_n24"] = p1_leg()
     if args.serving_requests > 0 and "serving" in legs:
         out["serving"] = serving_leg(args.serving_requests, args.serving_single,
                                      args.serving_slots,
-                                     calib=min(256, args.serving_requests))
+                                     calib=min(256, args.serving_requests),
+                                     no_cpu=args.no_cpu_baseline)
     if args.large_steps > 0 and "large" in legs:
-        out["large_state"] = large_state_leg(args.large_steps)
+        out["large_state"] = large_state_leg(args.large_steps, args.no_cpu_baseline)
     if args.dqaoa_cycles > 0 and "dqaoa" in legs:
         out["dqaoa"] = dqaoa_leg(args.dqaoa_cycles, args.no_cpu_baseline)
     if args.cobyla_subqubos > 0 and "cobyla" in legs:
@@ -607,7 +803,7 @@ def main():
     if args.maxcut_cycles > 0 and "maxcut" in legs:
         out["maxcut"] = maxcut_leg(args.maxcut_cycles)
     if args.grad_steps > 0 and "grad" in legs:
-        out["grad"] = grad_leg(args.grad_steps)
+        out["grad"] = grad_leg(args.grad_steps, args.no_cpu_baseline)
     print(json.dumps(out))
 
 
