@@ -218,7 +218,8 @@ def serving_leg(requests: int, one_at_a_time: int, max_slots: int, calib: int,
     batched = run(True, items, arr)
     if one_at_a_time < 0 or one_at_a_time > requests:
         one_at_a_time = requests
-    single = run(False, items[:one_at_a_time], arr[:one_at_a_time])
+    single = (run(False, items[:one_at_a_time], arr[:one_at_a_time]) if one_at_a_time > 0
+              else {"solves": 0})
     out = {
         "workload": (f"{requests} sub-QUBOs of one dense N={W['N']} QUBO, n~U{{"
                      f"{W['n_lo']}..{W['n_hi']}}}, p={p}, {evals} Adam evaluations + "

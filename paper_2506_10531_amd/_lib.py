@@ -108,17 +108,19 @@ class QueueStats(ctypes.Structure):
 _lib = None
 
 
-def load():
+def load(path: str | None = None):
     """Loads the in-tree libdqaoa.so; raises if it has not been built (there
-    is no fallback path)."""
+    is no fallback path).  ``path`` loads another build of the same sources
+    instead (e.g. one with host-side sanitizers), uncached."""
     global _lib
-    if _lib is not None:
+    if path is None and _lib is not None:
         return _lib
-    if not os.path.exists(SO):
+    so = path or SO
+    if not os.path.exists(so):
         raise RuntimeError(
-            f"{SO} is missing: build the HIP library first "
+            f"{so} is missing: build the HIP library first "
             "(python -c 'import __graft_entry__ as g; g.build()')")
-    L = ctypes.CDLL(SO)
+    L = ctypes.CDLL(so)
     vp, i, u64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_size_t
     dp = ctypes.c_void_p
     L.qaoa_last_error.restype = ctypes.c_char_p
@@ -159,7 +161,8 @@ def load():
         if name not in ("qaoa_last_error", "qaoa_version"):
             getattr(L, name).restype = ctypes.c_int
     L.qaoa_cycle_workspace.restype = sz
-    _lib = L
+    if path is None:
+        _lib = L
     return L
 
 
