@@ -63,7 +63,7 @@ __host__ __device__ constexpr uint32_t reg_off(int q) {
 }
 
 template <class G, int L>
-__device__ __forceinline__ uint32_t thread_bits(int lane, int wave) {
+__host__ __device__ __forceinline__ uint32_t thread_bits(int lane, int wave) {
   uint32_t l = 0;
 #pragma unroll
   for (int s = 0; s < 6; ++s) l |= (uint32_t)((lane >> s) & 1) << G::lane_bit(L, s);
@@ -109,7 +109,7 @@ __host__ __device__ constexpr int popc(unsigned m) {
 // Global offset of tile index l: set 0 tiles are bits [0, K); the others are
 // bits [0, C) plus [a, a + K - C).
 template <int C>
-__device__ __forceinline__ uint64_t dep(uint32_t l, int kind, int a) {
+__host__ __device__ __forceinline__ uint64_t dep(uint32_t l, int kind, int a) {
   if (kind == 1) return l;
   return (uint64_t)(l & ((1u << C) - 1u)) | ((uint64_t)(l >> C) << a);
 }
@@ -139,6 +139,22 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// LDS slot bases of a transpose X -> Y for one thread: the write base (its
+// layout-X lane and wave bits, relabelled by the mixed bits they hold when
+// flip) and the read base (likewise in layout Y).  A register pair q is then
+// written at wb + phys(reg_off<G, X>(q)) and read at rb + phys(reg_off<G, Y>(q)).
+template <class G, int X, int Y, int MIXLO>
+__host__ __device__ __forceinline__ void transpose_bases(int lane, int wave, bool flip,
+                                                         uint32_t& wb, uint32_t& rb) {
+  constexpr int K = Dim<G>::K;
+  constexpr uint32_t M = ((((1u << K) - 1u) >> MIXLO) << MIXLO) & ~1u;
+  constexpr uint32_t M1 = M & thread_mask<G, X>(), M2 = M & ~M1;
+  static_assert((M2 & ~thread_mask<G, Y>()) == 0, "a mixed bit is a register bit of both layouts");
+  static_assert((reg_bits_of<G, X>() & reg_bits_of<G, Y>()) == 1u, "layouts share only the pivot");
+  wb = phys((thread_bits<G, X>(lane, wave) ^ (flip ? M1 : 0u)) >> 1);
+  rb = phys((thread_bits<G, Y>(lane, wave) ^ (flip ? M2 : 0u)) >> 1);
+}
+
 // Move the tile from layout X to layout Y through LDS, one half at a time.
 // With flip, the tile is relabelled on the way: the amplitude at tile index l
 // moves to l ^ M, M = the mixed tile bits [MIXLO, K) without bit 0.  X and Y
@@ -148,15 +164,11 @@ __device__ __forceinline__ void lds_barrier() {
 template <class G, int X, int Y, int MIXLO>
 __device__ __forceinline__ void transpose(typename G::V (&v)[Dim<G>::NA], typename G::V* buf,
                                           int lane, int wave, bool flip) {
-  constexpr int K = Dim<G>::K, NP = Dim<G>::NP;
-  constexpr uint32_t M = ((((1u << K) - 1u) >> MIXLO) << MIXLO) & ~1u;
-  constexpr uint32_t M1 = M & thread_mask<G, X>(), M2 = M & ~M1;
-  static_assert((M2 & ~thread_mask<G, Y>()) == 0, "a mixed bit is a register bit of both layouts");
-  static_assert((reg_bits_of<G, X>() & reg_bits_of<G, Y>()) == 1u, "layouts share only the pivot");
-  const uint32_t tx = thread_bits<G, X>(lane, wave) ^ (flip ? M1 : 0u);
-  const uint32_t ty = thread_bits<G, Y>(lane, wave) ^ (flip ? M2 : 0u);
-  typename G::V* const bx = buf + phys(tx >> 1);
-  typename G::V* const by = buf + phys(ty >> 1);
+  constexpr int NP = Dim<G>::NP;
+  uint32_t wb, rb;
+  transpose_bases<G, X, Y, MIXLO>(lane, wave, flip, wb, rb);
+  typename G::V* const bx = buf + wb;
+  typename G::V* const by = buf + rb;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
 #pragma unroll
@@ -487,6 +499,18 @@ __device__ __forceinline__ void reduce_regs(const typename G::V (&v)[Dim<G>::NA]
   }
 }
 
+// Global offset, from the tile's block base, of register pair q of a thread
+// in layout L: its lane and wave part (pair_base) plus its register part
+// (pair_rel).  The two amplitudes of a pair are at that offset and the next.
+template <class G, int L>
+__host__ __device__ __forceinline__ uint64_t pair_base(int lane, int wave, int kind, int a) {
+  return dep<G::C>(thread_bits<G, L>(lane, wave), kind, a);
+}
+template <class G, int L>
+__host__ __device__ __forceinline__ uint64_t pair_rel(int q, int kind, int a) {
+  return dep<G::C>(reg_off<G, L>(q) << 1, kind, a);
+}
+
 // Global load/store of the register tile in layout L.  The two amplitudes of
 // a register pair differ in tile bit 0 and are adjacent in memory: one
 // 16-byte access for complex64, two for complex128.
@@ -494,10 +518,10 @@ template <class G, int L>
 __device__ __forceinline__ void load_tile(typename G::V (&v)[Dim<G>::NA], const typename G::V* base,
                                           int lane, int wave, int kind, int a) {
   using V = typename G::V;
-  const uint64_t tb = dep<G::C>(thread_bits<G, L>(lane, wave), kind, a);
+  const uint64_t tb = pair_base<G, L>(lane, wave, kind, a);
 #pragma unroll
   for (int q = 0; q < Dim<G>::NP; ++q) {
-    const uint64_t o = tb + dep<G::C>(reg_off<G, L>(q) << 1, kind, a);
+    const uint64_t o = tb + pair_rel<G, L>(q, kind, a);
     if constexpr (sizeof(V) == 8) {
       const float4 w = *reinterpret_cast<const float4*>(base + o);
       v[q << 1] = make_float2(w.x, w.y);
@@ -517,7 +541,7 @@ __device__ __forceinline__ void store_rows(const typename G::V (&v)[Dim<G>::NA],
   using V = typename G::V;
 #pragma unroll
   for (int q = 0; q < Dim<G>::NP; ++q) {
-    const uint64_t o = tb + dep<G::C>(reg_off<G, L>(q) << 1, kind, a);
+    const uint64_t o = tb + pair_rel<G, L>(q, kind, a);
     const V u = v[(q << 1) | SW], w = v[(q << 1) | !SW];
     if constexpr (sizeof(V) == 8) {
       *reinterpret_cast<float4*>(base + o) = make_float4(u.x, u.y, w.x, w.y);
@@ -531,7 +555,7 @@ template <class G, int L>
 __device__ __forceinline__ void store_tile(const typename G::V (&v)[Dim<G>::NA],
                                            typename G::V* base, int lane, int wave, int kind,
                                            int a, bool sw) {
-  const uint64_t tb = dep<G::C>(thread_bits<G, L>(lane, wave), kind, a);
+  const uint64_t tb = pair_base<G, L>(lane, wave, kind, a);
   if (sw) store_rows<G, L, true>(v, base, tb, kind, a);
   else store_rows<G, L, false>(v, base, tb, kind, a);
 }
@@ -546,7 +570,7 @@ __device__ __forceinline__ void store_prob_rows(const typename G::V (&v)[Dim<G>:
   using S = typename G::S;
 #pragma unroll
   for (int q = 0; q < Dim<G>::NP; ++q) {
-    const uint64_t o = tb + dep<G::C>(reg_off<G, L>(q) << 1, kind, a);
+    const uint64_t o = tb + pair_rel<G, L>(q, kind, a);
     const V u = v[(q << 1) | SW], w = v[(q << 1) | !SW];
     const S pu = scale * (u.x * u.x + u.y * u.y), pw = scale * (w.x * w.x + w.y * w.y);
     *reinterpret_cast<V*>(base + o) = mkv<V>(pu, pw);
@@ -556,7 +580,7 @@ template <class G, int L>
 __device__ __forceinline__ void store_probs(const typename G::V (&v)[Dim<G>::NA],
                                             typename G::S* base, int lane, int wave, int kind,
                                             int a, typename G::S scale, bool sw) {
-  const uint64_t tb = dep<G::C>(thread_bits<G, L>(lane, wave), kind, a);
+  const uint64_t tb = pair_base<G, L>(lane, wave, kind, a);
   if (sw) store_prob_rows<G, L, true>(v, base, tb, kind, a, scale);
   else store_prob_rows<G, L, false>(v, base, tb, kind, a, scale);
 }
@@ -576,7 +600,7 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
 // Block bits of tile ti (set kind 1: bits [K, n); kind 2: bits [C, a) and
 // [a + K - C, n)).
 template <int K, int C>
-__device__ __forceinline__ uint64_t tile_base(uint64_t ti, int kind, int a) {
+__host__ __device__ __forceinline__ uint64_t tile_base(uint64_t ti, int kind, int a) {
   if (kind == 1) return ti << K;
   const int gap = a - C;
   return ((ti & ((1ull << gap) - 1ull)) << C) | ((ti >> gap) << (a + K - C));
@@ -863,8 +887,11 @@ fwd_kernel(FwdArgs A) {
   constexpr int NT2 = PHASE ? (int)(sizeof(V) << G::R) / 8 : 0;
   const PassTab<G>* tab =
       reinterpret_cast<const PassTab<G>*>(static_cast<const char*>(A.tab) + st * TAB_BYTES);
+  // a lead-only pass has no phase and no reduction: it needs neither the
+  // folded Q nor the tile's tables
   stage_context<PT != P_LEAD ? NT1 + NT2 : 0>(
-      A.W + (size_t)(st / A.S) * n * n, n, A.coef + st * A.p, A.p, Wsh, cf, tid,
+      A.W + (size_t)(st / A.S) * n * n, PT == P_LEAD ? 0 : n, A.coef + st * A.p, A.p, Wsh, cf,
+      tid,
       [&] {
         if (PT != P_FIRST) load_tile<G, LA>(v, gin, lane, wave, KIND, d.a);
       },
@@ -877,7 +904,8 @@ fwd_kernel(FwdArgs A) {
       });
   // tile bit 0 flipped at PL (only when the pass mixes bit 0)
   const bool f0 = MIXLO == 0 && LEAD && cf[d.lead].mode != 0;
-  const double cblk = tile_context<K, G::C, KIND>(Wsh, n, d.a, zb, f0, fl, Wl, tmp, tid);
+  const double cblk =
+      PT == P_LEAD ? 0.0 : tile_context<K, G::C, KIND>(Wsh, n, d.a, zb, f0, fl, Wl, tmp, tid);
   if (PT != P_LEAD) {  // the tables' block-field entries
     for (int e = tid; e < Tables<G::R>::NF; e += NT) table_entry<G, PL>(&T, fl, Wl, e);
     lds_barrier();
