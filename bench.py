@@ -33,7 +33,7 @@ METRIC = ("amplitude-layer updates/s + HBM GB/s; sub-QUBO solves/s with p50/p99 
 # counter summary of each
 KERNEL_SRC = {
     "c64": [os.path.join(ROOT, "paper_2506_10531_amd", "csrc", f)
-            for f in ("fwd14.hip", "regtile.h")],
+            for f in ("fwd14.hip", "geom14.h", "regtile.h")],
     "c128": [os.path.join(ROOT, "paper_2506_10531_amd", "csrc", f)
              for f in ("fwd13d.hip", "geom13.h", "regtile.h")],
 }
