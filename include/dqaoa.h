@@ -207,10 +207,11 @@ int qaoa_profile_read(qaoa_ctx* ctx, int reset, long long* launches,
  * pending requests in FIFO order while a slot is free and the request's
  * device bytes (its 2^n-amplitude state, checkpoints and adjoint state) fit
  * in the queue's HBM budget; every step it advances all admitted requests
- * together, one batched kernel sequence per distinct n and evaluation (one
- * evaluation per step while a waiting request could be admitted, otherwise
- * up to 16), so requests that arrive while others run share the GPU.  A request's result does not depend
- * on which other requests share its steps. */
+ * together, one batched kernel sequence per distinct n and evaluation (up
+ * to 16 evaluations per step, enqueued with two in flight; from the third on
+ * the step ends early when a waiting request could be admitted), so
+ * requests that arrive while others run share the GPU.  A request's result
+ * does not depend on which other requests share its steps. */
 typedef struct {
   int max_slots;        /* requests resident at once (>= 1) */
   int max_pending;      /* queued requests before qaoa_submit reports QUEUE_FULL */

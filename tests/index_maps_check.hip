@@ -13,7 +13,9 @@
 //   * every LDS transpose the half-mixers make (with and without the cot-form
 //     relabelling) writes each slot of its half once, inside the buffer, and
 //     reads back into every register the amplitude that the target layout
-//     assigns to it (tile index l ^ M when relabelling).
+//     assigns to it (tile index l ^ M when relabelling);
+//   * the rounds of every half-mixer, in its lead and its trail order, mix
+//     each tile bit of the pass's range [MIXLO, K) exactly once and no other.
 // Prints "ok <checks>" and exits 0, or prints the first failures and exits 1.
 #include "../paper_2506_10531_amd/csrc/geom12.h"
 #include "../paper_2506_10531_amd/csrc/geom13.h"
@@ -157,6 +159,36 @@ void check_swaps(const char* g, int X, int Y, std::initializer_list<std::pair<in
   check(same, "register/lane exchanges map the layouts", g, X, Y);
 }
 
+// The rounds of a half-mixer, in the order the geometry runs them: layout L
+// mixes its register bits at or above the pass's first mixed bit that the
+// earlier rounds did not (reg_mask with DONE = the earlier layouts' register
+// bits).  Over the rounds every tile bit of [MIXLO, K) must be mixed exactly
+// once and no other bit.
+template <class G, int MIXLO, uint32_t DONE>
+void rounds(uint32_t&, bool&) {}
+template <class G, int MIXLO, uint32_t DONE, int L, int... Rest>
+void rounds(uint32_t& mixed, bool& twice) {
+  constexpr unsigned rm = reg_mask<G, L, DONE, MIXLO>();
+  for (int s = 0; s < G::R; ++s)
+    if ((rm >> s) & 1u) {
+      const uint32_t bit = 1u << G::reg_bit(L, s);
+      twice |= (mixed & bit) != 0;
+      mixed |= bit;
+    }
+  rounds<G, MIXLO, DONE | reg_bits_of<G, L>(), Rest...>(mixed, twice);
+}
+template <class G, int MIXLO, int... Ls>
+void check_rounds(const char* g) {
+  constexpr int K = Dim<G>::K;
+  uint32_t want = 0;
+  for (int b = MIXLO; b < K; ++b) want |= 1u << b;
+  uint32_t mixed = 0;
+  bool twice = false;
+  rounds<G, MIXLO, 0u, Ls...>(mixed, twice);
+  check(!twice, "no tile bit mixed twice in a half-mixer", g, MIXLO);
+  check(mixed == want, "a half-mixer mixes exactly its bits", g, MIXLO, mixed);
+}
+
 // ---- geometries --------------------------------------------------------------
 
 using G13D = G13T<double2, double, 2>;
@@ -200,6 +232,8 @@ template <class G, int M>
 void transposes_set0_seq() {
   check_transpose<G, G::L_A1, G::L_B, M>("A1->B");
   check_transpose<G, G::L_B, G::L_A1, M>("B->A1");
+  check_rounds<G, M, G::L_A, G::L_A1, G::L_B, G::L_B1>("set-0 sequence, lead");
+  check_rounds<G, M, G::L_B1, G::L_B, G::L_A1, G::L_A>("set-0 sequence, trail");
 }
 template <class G, int M>
 void transposes_b2_seq() {
@@ -207,13 +241,25 @@ void transposes_b2_seq() {
   check_transpose<G, G::L_B2, G::L_A, M>("B2->A");
 }
 
+template <class G, int M>
+void g14_b2(const char* g) {
+  transposes_b2_seq<G, M>();
+  check_rounds<G, M, G::L_A, G::L_B2>(g);
+  check_rounds<G, M, G::L_B2, G::L_A>(g);
+}
+template <class G, int M>
+void g13_b2(const char* g) {
+  transposes_b2_seq<G, M>();
+  check_rounds<G, M, G::L_A, G::L_B2, G::L_B3>(g);
+  check_rounds<G, M, G::L_B3, G::L_B2, G::L_A>(g);
+}
 template <int... Ms>
 void g14_kind2(std::integer_sequence<int, Ms...>) {
-  (transposes_b2_seq<G14T<(Ms < 8 ? Ms : 8)>, Ms>(), ...);
+  (g14_b2<G14T<(Ms < 8 ? Ms : 8)>, Ms>("G14T kind 2"), ...);
 }
 template <int... Ms>
 void g13c_kind2(std::integer_sequence<int, Ms...>) {
-  (transposes_b2_seq<G13C<(Ms < 8 ? Ms : 8)>, Ms>(), ...);
+  (g13_b2<G13C<(Ms < 8 ? Ms : 8)>, Ms>("G13T kind 2"), ...);
 }
 template <int... Ms>
 void g13d_kind2(std::integer_sequence<int, Ms...>) {

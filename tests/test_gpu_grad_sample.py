@@ -43,7 +43,8 @@ GRAD_CASES = [("c128", 3, 1), ("c128", 8, 3), ("c128", 12, 2), ("c128", 13, 2),
               ("c128", 14, 1), ("c128", 16, 3), ("c128", 17, 4), ("c128", 18, 2),
               ("c128", 20, 6), ("c128", 22, 2), ("c64", 5, 2), ("c64", 13, 4),
               ("c64", 14, 2), ("c64", 15, 1), ("c64", 16, 6), ("c64", 17, 5),
-              ("c64", 19, 3), ("c64", 22, 2)]
+              ("c64", 18, 3), ("c64", 19, 3), ("c64", 20, 2), ("c64", 21, 1),
+              ("c64", 22, 2)]
 
 
 @pytest.mark.parametrize("prec,n,p", GRAD_CASES)
