@@ -375,8 +375,9 @@ int qaoa_queue::step() {
   if (res_off > hRes_bytes)
     return set_error(QAOA_ERR_OUT_OF_MEMORY, "step results exceed the staging buffer");
   // evaluation rounds: round k enqueues one evaluation of every group on the
-  // group's stream; from round 2 on, the host first waits for round k - 2 and
-  // ends the step there if a waiting request could now be admitted
+  // group's stream; from the third round (k = 2) on, the host first waits
+  // for round k - 2 and ends the step there if a waiting request could now
+  // be admitted
   gi = 0;
   for (auto& kv : groups) {
     hipStream_t s = streams[gi % NSTREAMS];
