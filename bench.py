@@ -241,8 +241,9 @@ def serving_leg(requests: int, one_at_a_time: int, max_slots: int, calib: int,
 def plain_leg(no_cpu: bool):
     """The plain form: one dense n = 10 QUBO, p = 2, 64 parameter sets,
     complex128, <C> and the full probability vector of every set (one
-    qaoa_expect per call).  Small enough that every state lives in one LDS
-    tile: the call is bound by FP64 VALU work and launch latency, not HBM, so
+    qaoa_expect per call).  Small enough that every state lives in one
+    work-group's registers (one launch per call): the call is bound by FP64
+    VALU latency and launch overhead, not HBM, so
     it reports updates/s and the FP64 rate of the counted arithmetic (6n
     flops of mixer butterflies and 6 of the phase multiply per
     amplitude-layer) against MI355X's 78.6 TFLOP/s FP64 vector peak."""

@@ -479,6 +479,15 @@ int enqueue_expect(const Layout& L, char* base, const double* Q,
                    const double* gammas, const double* betas, double* expect,
                    double* norm, void* probs, void* psi, hipStream_t s,
                    PassTimer* tm) {
+  if (L.plan.npass == 1 && L.n <= SMALL_NMAX && !fwd_reg_off()) {
+    // the whole state in one work-group's registers: one launch, no scratch
+    const double out = (double)L.state_bytes * L.nstates * ((probs ? 0.5 : 0.0) + (psi ? 1.0 : 0.0));
+    TimerScope ts(tm, s, out);
+    hipError_t e = launch_small_expect(L.prec, L.n, L.p, L.S, (int)L.nstates, Q, gammas, betas,
+                                       expect, norm, probs, psi, s);
+    if (e != hipSuccess) return hip_error(e, "whole-state evaluation");
+    return QAOA_OK;
+  }
   int rc = run_forward(L, base, Q, gammas, betas, probs, psi, s, tm);
   if (rc) return rc;
   const PassDesc& last = L.plan.pass[L.plan.npass - 1];
@@ -916,6 +925,21 @@ int qaoa_expect(qaoa_ctx* ctx, int prec, int B, int n, int p, int S,
   if (rc) return rc;
   if (!Q || !gammas || !betas || !expect)
     return set_error(QAOA_ERR_INVALID_ARG, "Q, gammas, betas and expect must be non-NULL");
+  if (n <= SMALL_NMAX && !fwd_reg_off()) {
+    // the whole state in one work-group's registers: no plan and no scratch
+    if (ctx->device < 0) return set_error(QAOA_ERR_NO_DEVICE, "host-only context");
+    DeviceGuard g(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    {
+      const size_t amp = prec == QAOA_C64 ? 8 : 16;
+      TimerScope ts(ctx->timer(), s, probs ? 0.5 * amp * ((double)B * S) * (double)(1ull << n) : 0.0);
+      e = launch_small_expect(prec, n, p, S, B * S, Q, gammas, betas, expect, norm, probs,
+                              nullptr, s);
+    }
+    if (e == hipSuccess) e = hipGetLastError();
+    return e == hipSuccess ? QAOA_OK : hip_error(e, "whole-state evaluation");
+  }
   Layout L;
   rc = prepare_call(ctx, OP_EXPECT, prec, B, n, p, S, 0, &L);
   if (rc) return rc;

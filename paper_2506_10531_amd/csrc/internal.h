@@ -190,6 +190,13 @@ hipError_t launch_prep(int nprob, int n, const double* Q, double* W,
                        const double* betas, LayerCoef* coef,
                        hipStream_t stream);
 
+// Whole-state evaluation for n <= SMALL_NMAX (small.hip): the fold of Q, the
+// p layers, <C> and the norm, and the optional probabilities and state, in
+// one launch of one work-group per state.
+constexpr int SMALL_NMAX = 12;
+hipError_t launch_small_expect(int prec, int n, int p, int S, int nstates, const double* Q,
+                               const double* gammas, const double* betas, double* expect,
+                               double* norm, void* probs, void* psi, hipStream_t stream);
 hipError_t launch_fwd_pass(int prec, const PassDesc& d, int nstates, int S,
                            int p, const void* in, void* out,
                            uint64_t state_stride, const double* W,

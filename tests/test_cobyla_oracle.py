@@ -15,7 +15,7 @@ import pytest
 from scipy.optimize import minimize
 
 from oracle import expect
-from oracle.cobyla_loop import cobyla_loop, cobyla_min
+from oracle.cobyla_loop import cobyla_loop, cobyla_min, divergence
 
 
 @pytest.mark.parametrize("q", [1.5, -0.7])
@@ -123,3 +123,48 @@ def test_golden_covers_every_rule():
     for event in ("becomes x0", "drops vertex", "rho ->", "rho is rhoend: stop",
                   "(|d", "(face distance", "g.v = -"):
         assert event in text, event
+
+
+def _perturbed(f, delta, k):
+    """f plus a deterministic +-delta that depends on the point and on k."""
+    import hashlib
+
+    def g(x):
+        h = hashlib.sha256(bytes([k]) + np.ascontiguousarray(x, dtype=np.float64).tobytes())
+        return f(x) + (delta if h.digest()[0] & 1 else -delta)
+    return g
+
+
+def test_margins_flag_every_divergence():
+    """The trace's decision margins are lower bounds of the objective change
+    that flips a decision: wherever a run with its objective moved by
+    +-delta leaves the unperturbed run, the decision taken there had a
+    margin of at most 2 delta plus what the point drift accumulated before it
+    moves the objective (2 gn drift), or a simplex test within a few times
+    that drift of its threshold."""
+    diverged = 0
+    for seed in range(6):
+        rng = np.random.default_rng(200 + seed)
+        n, p = 5, 1 + seed % 2
+        A = rng.uniform(-1, 1, size=(n, n))
+        Q = np.triu(A) + np.triu(A, 1).T
+        th0 = np.concatenate([rng.uniform(0, np.pi, p), rng.uniform(0, np.pi / 2, p)])
+
+        def f(x, Q=Q, p=p):
+            return float(expect(Q, x[None, :p], x[None, p:])[0][0])
+
+        tr = []
+        cobyla_min(f, th0, 0.5, 1e-6, 120, trace=tr)
+        for delta in (1e-12, 1e-10):
+            for k in range(3):
+                other = []
+                cobyla_min(_perturbed(f, delta, k), th0, 0.5, 1e-6, 120, trace=other)
+                kd, drift = divergence(tr, [r["x"] for r in other])
+                if kd == len(tr) == len(other):
+                    continue
+                diverged += 1
+                r = tr[kd - 1]
+                assert (r["margin"] <= 2 * delta + 2 * r["gn"] * drift
+                        or r["gmargin"] <= 4 * drift), \
+                    (seed, delta, k, kd, r["margin"], r["gn"], r["gmargin"], drift)
+    assert diverged >= 3  # the check saw divergences to explain

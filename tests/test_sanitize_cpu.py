@@ -17,7 +17,7 @@ CSRC = os.path.join(ROOT, "paper_2506_10531_amd", "csrc")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CLANG = "/opt/rocm/llvm/bin/clang"
 HOST_UNITS = ("capi", "queue", "cobyla", "cycle", "objective")
-KERNEL_UNITS = ("fwd14", "fwd13d", "grad12", "grad13", "kernels")
+KERNEL_UNITS = ("fwd14", "fwd13d", "grad12", "grad13", "kernels", "small")
 SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
        "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
 
