@@ -304,6 +304,10 @@ static bool grad_reg_off() {
 // Register-tile gradients: complex64 on 13-qubit tiles (14 <= n <= 22),
 // complex128 on 12-qubit tiles (13 <= n <= 22); DQAOA_GRAD_KERNEL=lds
 // selects the LDS-tile adjoint instead.
+// Whole-state adjoint (small.hip) for n up to this size; DQAOA_GRAD_KERNEL=lds
+// selects the LDS-tile adjoint instead.
+static int small_grad_nmax() { return grad_reg_off() ? 0 : SMALL_NMAX; }
+
 static bool use_reg13(int op, int prec, int n) {
   return !grad_reg_off() && op == OP_GRAD && prec == QAOA_C64 && n >= 14 && n <= 22;
 }
@@ -524,6 +528,13 @@ int enqueue_sample(const Layout& L, char* base, const double* Q,
 int enqueue_grad(const Layout& L, char* base, const double* Q,
                  const double* gammas, const double* betas, double* expect,
                  double* dgamma, double* dbeta, hipStream_t s, PassTimer* tm) {
+  if (L.n <= small_grad_nmax()) {
+    // psi and lambda of the whole state in one work-group's registers
+    TimerScope ts(tm, s, 0.0);
+    hipError_t e = launch_small_grad(L.prec, L.n, L.p, L.S, (int)L.nstates, Q, gammas, betas,
+                                     expect, dgamma, dbeta, s);
+    return e == hipSuccess ? QAOA_OK : hip_error(e, "whole-state gradient");
+  }
   double* W = (double*)L.at(base, L.iW);
   LayerCoef* coef = (LayerCoef*)L.at(base, L.iC);
   double* part = (double*)L.at(base, L.iPart);
@@ -1032,6 +1043,19 @@ int qaoa_grad(qaoa_ctx* ctx, int prec, int B, int n, int p, int S,
   if (rc) return rc;
   if (!Q || !gammas || !betas || !dgamma || !dbeta)
     return set_error(QAOA_ERR_INVALID_ARG, "Q, gammas, betas, dgamma and dbeta must be non-NULL");
+  if (n <= small_grad_nmax()) {
+    // the whole state in one work-group's registers: no plan and no scratch
+    if (ctx->device < 0) return set_error(QAOA_ERR_NO_DEVICE, "host-only context");
+    DeviceGuard g(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    {
+      TimerScope ts(ctx->timer(), s, 0.0);
+      e = launch_small_grad(prec, n, p, S, B * S, Q, gammas, betas, expect, dgamma, dbeta, s);
+    }
+    if (e == hipSuccess) e = hipGetLastError();
+    return e == hipSuccess ? QAOA_OK : hip_error(e, "whole-state gradient");
+  }
   Layout L;
   rc = prepare_call(ctx, OP_GRAD, prec, B, n, p, S, 0, &L);
   if (rc) return rc;

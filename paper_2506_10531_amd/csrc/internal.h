@@ -197,6 +197,10 @@ constexpr int SMALL_NMAX = 12;
 hipError_t launch_small_expect(int prec, int n, int p, int S, int nstates, const double* Q,
                                const double* gammas, const double* betas, double* expect,
                                double* norm, void* probs, void* psi, hipStream_t stream);
+// The adjoint gradient of the same states (expect nullable), one launch.
+hipError_t launch_small_grad(int prec, int n, int p, int S, int nstates, const double* Q,
+                             const double* gammas, const double* betas, double* expect,
+                             double* dgamma, double* dbeta, hipStream_t stream);
 hipError_t launch_fwd_pass(int prec, const PassDesc& d, int nstates, int S,
                            int p, const void* in, void* out,
                            uint64_t state_stride, const double* W,

@@ -1,4 +1,5 @@
-// Whole-state evaluation of small states (n <= 12) in one launch (gfx950).
+// Whole-state evaluation and adjoint gradient of small states (n <= 12) in
+// one launch (gfx950).
 //
 // A state of 2^n amplitudes fits the registers of one work-group: thread t of
 // T = 2^min(n, 8) threads holds amplitudes z = t + 256 r, r < 2^(n - 8), so
@@ -52,30 +53,28 @@ __device__ __forceinline__ V mix1(V a, V b, S c, S s) {
   return r;
 }
 
-// LDS bytes: folded Q, per-layer (gamma / 2 pi, cos beta, sin beta), the
-// reduction slots, and the amplitudes when there are wave qubits.
+// LDS: the folded Q, per-layer (gamma / 2 pi, cos beta, sin beta), the
+// reduction slots (and, for the gradient, per-layer per-wave sums), then
+// the amplitudes (psi, and lambda for the gradient) when there are wave
+// qubits.
+__host__ __device__ inline size_t small_head(int n, int p, int grad) {
+  const size_t head = ((size_t)n * n + 3 * (size_t)p + 8 + (grad ? 8 * (size_t)p : 0)) * 8;
+  return (head + 15) & ~(size_t)15;
+}
 template <class V>
-size_t small_lds(int n, int p) {
-  const size_t head = ((size_t)n * n + 3 * (size_t)p + 8) * sizeof(double);
-  const size_t h16 = (head + 15) & ~(size_t)15;
-  return h16 + (n > 6 ? ((size_t)1 << n) * sizeof(V) : 0);
+size_t small_lds(int n, int p, int grad) {
+  return small_head(n, p, grad) + (n > 6 ? ((size_t)1 << n) * sizeof(V) * (grad ? 2 : 1) : 0);
 }
 
-template <class V, int NR>
-__global__ void __launch_bounds__(256) small_kernel(SmallArgs A) {
-  using S = typename std::conditional<sizeof(V) == 8, float, double>::type;
+// Folds Q into LDS (W_ii = Q_ii, W_ij = Q_ij + Q_ji, so that C(z) =
+// sum_i W_ii z_i + sum_{i<j} W_ij z_i z_j), stages (gamma / 2 pi, cos beta,
+// sin beta) per layer and forms C(z) of the thread's amplitudes (FP64).
+template <int NR>
+__device__ __forceinline__ void small_setup(const SmallArgs& A, double* Wsh, double* cs,
+                                            double (&C)[1 << NR]) {
   constexpr int NAMP = 1 << NR;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int n = A.n, p = A.p;
-  const int T = blockDim.x, tid = threadIdx.x;
+  const int n = A.n, p = A.p, T = blockDim.x, tid = threadIdx.x;
   const uint64_t st = blockIdx.x;
-  double* const Wsh = reinterpret_cast<double*>(smem);
-  double* const cs = Wsh + n * n;
-  double* const red = cs + 3 * p;
-  const size_t head = ((size_t)n * n + 3 * (size_t)p + 8) * sizeof(double);
-  V* const buf = reinterpret_cast<V*>(smem + ((head + 15) & ~(size_t)15));
-
-  // W_ii = Q_ii, W_ij = Q_ij + Q_ji: C(z) = sum_i W_ii z_i + sum_{i<j} W_ij z_i z_j
   const double* Q = A.Q + (st / A.S) * n * n;
   for (int e = tid; e < n * n; e += T) {
     const int i = e / n, j = e - i * n;
@@ -89,10 +88,9 @@ __global__ void __launch_bounds__(256) small_kernel(SmallArgs A) {
     cs[3 * j + 2] = s;
   }
   __syncthreads();
-
-  // C(z) of this thread's amplitudes: the low bits (the thread index), the
-  // register bits' fields from them, and the couplings among register bits
-  // (unrolled over the 8 low bits, so that the LDS reads issue together)
+  // the low bits (the thread index; unrolled over 8 so that the LDS reads
+  // issue together), the register bits' fields from them, and the couplings
+  // among register bits
   const int nb = n < 8 ? n : 8;
   double cbase = 0.0;
 #pragma unroll
@@ -103,34 +101,39 @@ __global__ void __launch_bounds__(256) small_kernel(SmallArgs A) {
       for (int j = 0; j < i; ++j)
         if ((tid >> j) & 1) cbase += Wsh[i * n + j];
     }
-  double C[NAMP];
-  {
-    double f[NR > 0 ? NR : 1];
+  double f[NR > 0 ? NR : 1];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      const int i = 8 + k;
-      double x = Wsh[i * n + i];
+  for (int k = 0; k < NR; ++k) {
+    const int i = 8 + k;
+    double x = Wsh[i * n + i];
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if ((tid >> j) & 1) x += Wsh[i * n + j];
-      f[k] = x;
-    }
-#pragma unroll
-    for (int r = 0; r < NAMP; ++r) {
-      double c = cbase;
-#pragma unroll
-      for (int k = 0; k < NR; ++k)
-        if ((r >> k) & 1) {
-          c += f[k];
-#pragma unroll
-          for (int k2 = 0; k2 < k; ++k2)
-            if ((r >> k2) & 1) c += Wsh[(8 + k) * n + 8 + k2];
-        }
-      C[r] = c;
-    }
+    for (int j = 0; j < 8; ++j)
+      if ((tid >> j) & 1) x += Wsh[i * n + j];
+    f[k] = x;
   }
+#pragma unroll
+  for (int r = 0; r < NAMP; ++r) {
+    double c = cbase;
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+      if ((r >> k) & 1) {
+        c += f[k];
+#pragma unroll
+        for (int k2 = 0; k2 < k; ++k2)
+          if ((r >> k2) & 1) c += Wsh[(8 + k) * n + 8 + k2];
+      }
+    C[r] = c;
+  }
+}
 
-  V v[NAMP];
+// The p layers from |+>: phase e^{-i gamma C(z)}, then the mixer on every
+// qubit.
+template <class V, int NR>
+__device__ __forceinline__ void small_layers(V (&v)[1 << NR], const double (&C)[1 << NR],
+                                             const double* cs, V* buf, int n, int p) {
+  using S = typename std::conditional<sizeof(V) == 8, float, double>::type;
+  constexpr int NAMP = 1 << NR;
+  const int tid = threadIdx.x;
   const double a0 = exp2(-0.5 * (double)n);
 #pragma unroll
   for (int r = 0; r < NAMP; ++r) v[r] = mkv<V>(a0, 0.0);
@@ -176,6 +179,38 @@ __global__ void __launch_bounds__(256) small_kernel(SmallArgs A) {
           v[r | (1 << k)] = mix1(x1, x0, c, s);
         }
   }
+}
+
+// Sum of x over the work-group's threads into red[] (one slot per wave),
+// returned on thread 0.
+__device__ __forceinline__ double small_sum(double x, double* red) {
+  const int T = blockDim.x, tid = threadIdx.x;
+  const int wl = T < 64 ? T : 64;
+  for (int off = wl >> 1; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = x;
+  __syncthreads();
+  double sum = 0.0;
+  if (tid == 0)
+    for (int w = 0; w < (T + 63) / 64; ++w) sum += red[w];
+  __syncthreads();
+  return sum;
+}
+
+template <class V, int NR>
+__global__ void __launch_bounds__(256) small_kernel(SmallArgs A) {
+  using S = typename std::conditional<sizeof(V) == 8, float, double>::type;
+  constexpr int NAMP = 1 << NR;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n = A.n, p = A.p, tid = threadIdx.x;
+  const uint64_t st = blockIdx.x;
+  double* const Wsh = reinterpret_cast<double*>(smem);
+  double* const cs = Wsh + n * n;
+  double* const red = cs + 3 * p;
+  V* const buf = reinterpret_cast<V*>(smem + small_head(n, p, 0));
+  double C[NAMP];
+  small_setup<NR>(A, Wsh, cs, C);
+  V v[NAMP];
+  small_layers<V, NR>(v, C, cs, buf, n, p);
 
   // outputs: probabilities and state in the state precision, <C> and the
   // norm in FP64
@@ -190,51 +225,182 @@ __global__ void __launch_bounds__(256) small_kernel(SmallArgs A) {
     if (A.probs) static_cast<S*>(A.probs)[z] = (S)pz;
     if (A.psi) static_cast<V*>(A.psi)[z] = v[r];
   }
-  const int wl = T < 64 ? T : 64;
-  for (int off = wl >> 1; off > 0; off >>= 1) {
-    ae += __shfl_xor(ae, off, 64);
-    an += __shfl_xor(an, off, 64);
-  }
-  if ((tid & 63) == 0) {
-    red[2 * (tid >> 6)] = ae;
-    red[2 * (tid >> 6) + 1] = an;
-  }
-  __syncthreads();
+  const double se = small_sum(ae, red), sn = small_sum(an, red + 4);
   if (tid == 0) {
-    double se = 0.0, sn = 0.0;
-    for (int w = 0; w < (T + 63) / 64; ++w) {
-      se += red[2 * w];
-      sn += red[2 * w + 1];
-    }
     A.expect[st] = se;
     if (A.norm) A.norm[st] = sn;
   }
 }
 
+// The adjoint gradient of <C> (Eq. (1)) with respect to every gamma_j and
+// beta_j of Eq. (2): the forward layers, lambda = C psi, then for j = p..1
+// the mixer undone on psi and lambda with d<C>/dbeta_j = -2 sum_q Im
+// <lambda| X_q |psi> taken from the partner amplitudes each qubit's undo
+// fetches (X_q commutes with the layer's mixer, so any point of its undo
+// gives the same value), d<C>/dgamma_j = 2 Im <lambda| C |psi> where the
+// phase was applied, and the phase undone.  FP64 sums; the per-layer sums
+// of each wave go to LDS and are added at the end.
+template <class V, int NR>
+__global__ void __launch_bounds__(256) small_grad_kernel(SmallArgs A, double* dgamma,
+                                                        double* dbeta) {
+  using S = typename std::conditional<sizeof(V) == 8, float, double>::type;
+  constexpr int NAMP = 1 << NR;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n = A.n, p = A.p, T = blockDim.x, tid = threadIdx.x;
+  const int wave = tid >> 6, nwaves = (T + 63) / 64;
+  const uint64_t st = blockIdx.x;
+  double* const Wsh = reinterpret_cast<double*>(smem);
+  double* const cs = Wsh + n * n;
+  double* const red = cs + 3 * p;
+  double* const acc = red + 8;  // [2p][4]: per layer and wave, dgamma then dbeta sums
+  V* const buf = reinterpret_cast<V*>(smem + small_head(n, p, 1));
+  V* const bufl = buf + (n > 6 ? (1 << n) : 0);
+  double C[NAMP];
+  small_setup<NR>(A, Wsh, cs, C);
+  V v[NAMP], l[NAMP];
+  small_layers<V, NR>(v, C, cs, buf, n, p);
+  double ae = 0.0;
+#pragma unroll
+  for (int r = 0; r < NAMP; ++r) {
+    ae = fma((double)v[r].x * v[r].x + (double)v[r].y * v[r].y, C[r], ae);
+    const S cz = (S)C[r];
+    l[r] = mkv<V>(cz * v[r].x, cz * v[r].y);
+  }
+  // Im(conj(a) b)
+  auto imc = [](V a, V b) { return (double)a.x * b.y - (double)a.y * b.x; };
+  const int nl = n < 6 ? n : 6, nw = n <= 6 ? 0 : (n == 7 ? 1 : 2);
+  for (int j = p - 1; j >= 0; --j) {
+    const double gp = cs[3 * j];
+    const S c = (S)cs[3 * j + 1], s = (S)cs[3 * j + 2];
+    double xb = 0.0;  // sum_q Im <lambda| X_q |psi>
+    // the mixer undone: e^{-i beta X} = c - i s X per qubit
+    for (int q = 0; q < nl; ++q) {
+#pragma unroll
+      for (int r = 0; r < NAMP; ++r) {
+        const V vp = shfl_xor_v(v[r], 1 << q), lp = shfl_xor_v(l[r], 1 << q);
+        xb += imc(l[r], vp);
+        v[r] = mix1(v[r], vp, c, (S)-s);
+        l[r] = mix1(l[r], lp, c, (S)-s);
+        // bound the shuffles in flight (each holds two partner amplitudes)
+        if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    if (nw) {
+#pragma unroll
+      for (int r = 0; r < NAMP; ++r) {
+        buf[(r << 8) | tid] = v[r];
+        bufl[(r << 8) | tid] = l[r];
+      }
+      __syncthreads();
+      if (nw == 1) {
+#pragma unroll
+        for (int r = 0; r < NAMP; ++r) {
+          const int z = ((r << 8) | tid) ^ 64;
+          const V vp = buf[z], lp = bufl[z];
+          xb += imc(l[r], vp);
+          v[r] = mix1(v[r], vp, c, (S)-s);
+          l[r] = mix1(l[r], lp, c, (S)-s);
+        }
+      } else {
+        // (c - i s X) (x) (c - i s X): c^2 a - i c s (a6 + a7) - s^2 a67
+        const S cc = c * c, ss = s * s, sc = s * c;
+        auto undo2 = [&](V a, V b6, V b7, V b67) {
+          const S ux = b6.x + b7.x, uy = b6.y + b7.y;
+          V o;
+          o.x = fma(cc, a.x, fma(sc, uy, -ss * b67.x));
+          o.y = fma(cc, a.y, fma(-sc, ux, -ss * b67.y));
+          return o;
+        };
+#pragma unroll
+        for (int r = 0; r < NAMP; ++r) {
+          const int z = (r << 8) | tid;
+          const V v6 = buf[z ^ 64], v7 = buf[z ^ 128], v67 = buf[z ^ 192];
+          const V l6 = bufl[z ^ 64], l7 = bufl[z ^ 128], l67 = bufl[z ^ 192];
+          xb += imc(l[r], v6) + imc(l[r], v7);
+          v[r] = undo2(v[r], v6, v7, v67);
+          l[r] = undo2(l[r], l6, l7, l67);
+          if ((r & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+#pragma unroll
+      for (int r = 0; r < NAMP; ++r)
+        if (!((r >> k) & 1)) {
+          const int r1 = r | (1 << k);
+          xb += imc(l[r], v[r1]) + imc(l[r1], v[r]);
+          const V v0 = v[r], v1 = v[r1], l0 = l[r], l1 = l[r1];
+          v[r] = mix1(v0, v1, c, (S)-s);
+          v[r1] = mix1(v1, v0, c, (S)-s);
+          l[r] = mix1(l0, l1, c, (S)-s);
+          l[r1] = mix1(l1, l0, c, (S)-s);
+        }
+    // 2 Im <lambda| C |psi> where the phase was applied, then the phase undone
+    double xg = 0.0;
+#pragma unroll
+    for (int r = 0; r < NAMP; ++r) {
+      xg = fma(imc(l[r], v[r]), C[r], xg);
+      const V u = unitv<V>(-gp * C[r]);
+      v[r] = cmul(v[r], u);
+      l[r] = cmul(l[r], u);
+    }
+    const int wl = T < 64 ? T : 64;
+    for (int off = wl >> 1; off > 0; off >>= 1) {
+      xg += __shfl_xor(xg, off, 64);
+      xb += __shfl_xor(xb, off, 64);
+    }
+    if ((tid & 63) == 0) {
+      acc[(2 * j) * 4 + wave] = xg;
+      acc[(2 * j + 1) * 4 + wave] = xb;
+    }
+  }
+  const double se = small_sum(ae, red);
+  if (tid == 0 && A.expect) A.expect[st] = se;
+  for (int j = tid; j < p; j += T) {
+    double g = 0.0, b = 0.0;
+    for (int w = 0; w < nwaves; ++w) {
+      g += acc[(2 * j) * 4 + w];
+      b += acc[(2 * j + 1) * 4 + w];
+    }
+    dgamma[st * p + j] = 2.0 * g;
+    dbeta[st * p + j] = -2.0 * b;
+  }
+}
+
 template <class V>
-hipError_t launch_small_t(const SmallArgs& A, int nstates, hipStream_t stream) {
+hipError_t launch_small_t(const SmallArgs& A, int nstates, double* dgamma, double* dbeta,
+                          hipStream_t stream) {
   const int n = A.n;
+  const bool grad = dgamma != nullptr;
   const dim3 grid((unsigned)nstates), blk(1u << (n < 8 ? n : 8));
-  const size_t lds = small_lds<V>(n, A.p);
-#define DQ_S(NR)                                                                        \
-  do {                                                                                  \
-    if (lds > 65536) {                                                                  \
-      hipError_t e = hipFuncSetAttribute((const void*)small_kernel<V, NR>,              \
-                                         hipFuncAttributeMaxDynamicSharedMemorySize,    \
-                                         (int)lds);                                     \
-      if (e != hipSuccess) return e;                                                    \
-    }                                                                                   \
-    hipLaunchKernelGGL((small_kernel<V, NR>), grid, blk, lds, stream, A);               \
-  } while (0)
+  const size_t lds = small_lds<V>(n, A.p, grad ? 1 : 0);
+  auto go = [&](auto kern, auto... args) -> hipError_t {
+    if (lds > 65536) {
+      hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, grid, blk, lds, stream, A, args...);
+    return hipGetLastError();
+  };
+#define DQ_S(NR)                                                              \
+  return grad ? go(small_grad_kernel<V, NR>, dgamma, dbeta) : go(small_kernel<V, NR>)
   switch (n <= 8 ? 0 : n - 8) {
-    case 0: DQ_S(0); break;
-    case 1: DQ_S(1); break;
-    case 2: DQ_S(2); break;
-    case 3: DQ_S(3); break;
-    default: DQ_S(4); break;
+    case 0: DQ_S(0);
+    case 1: DQ_S(1);
+    case 2: DQ_S(2);
+    case 3: DQ_S(3);
+    default: DQ_S(4);
   }
 #undef DQ_S
-  return hipGetLastError();
+}
+
+bool small_args_ok(int n, int p, int S, int nstates, const double* Q, const double* gammas,
+                   const double* betas) {
+  return n >= 1 && n <= SMALL_NMAX && p >= 1 && p <= 64 && S >= 1 && nstates >= 1 && Q &&
+         gammas && betas;
 }
 
 }  // namespace
@@ -242,12 +408,20 @@ hipError_t launch_small_t(const SmallArgs& A, int nstates, hipStream_t stream) {
 hipError_t launch_small_expect(int prec, int n, int p, int S, int nstates, const double* Q,
                                const double* gammas, const double* betas, double* expect,
                                double* norm, void* probs, void* psi, hipStream_t stream) {
-  if (n < 1 || n > SMALL_NMAX || p < 1 || p > 64 || S < 1 || nstates < 1 || !Q || !gammas ||
-      !betas || !expect)
-    return hipErrorInvalidValue;
+  if (!small_args_ok(n, p, S, nstates, Q, gammas, betas) || !expect) return hipErrorInvalidValue;
   SmallArgs A{n, p, S, Q, gammas, betas, expect, norm, probs, psi};
-  return prec == QAOA_C64 ? launch_small_t<float2>(A, nstates, stream)
-                          : launch_small_t<double2>(A, nstates, stream);
+  return prec == QAOA_C64 ? launch_small_t<float2>(A, nstates, nullptr, nullptr, stream)
+                          : launch_small_t<double2>(A, nstates, nullptr, nullptr, stream);
+}
+
+hipError_t launch_small_grad(int prec, int n, int p, int S, int nstates, const double* Q,
+                             const double* gammas, const double* betas, double* expect,
+                             double* dgamma, double* dbeta, hipStream_t stream) {
+  if (!small_args_ok(n, p, S, nstates, Q, gammas, betas) || !dgamma || !dbeta)
+    return hipErrorInvalidValue;
+  SmallArgs A{n, p, S, Q, gammas, betas, expect, nullptr, nullptr, nullptr};
+  return prec == QAOA_C64 ? launch_small_t<float2>(A, nstates, dgamma, dbeta, stream)
+                          : launch_small_t<double2>(A, nstates, dgamma, dbeta, stream);
 }
 
 }  // namespace dq
