@@ -1,0 +1,86 @@
+"""GPU cost values C(z) for every z, read out of the state, against the oracle.
+
+With every beta_j = 0 the mixers of Eq. (2) are the identity, so the state is
+2^{-n/2} exp(-i (gamma_1 + ... + gamma_p) C(z)) at every z: its phase is the
+cost the kernels built from their per-state tables.  With the gammas summing
+to g0 = 1 / max_z |C(z)| the phase stays in [-1, 1] (no wrap), and
+C_gpu(z) = -arg(psi(z)) / g0 recovers the GPU's C(z) at every index.
+
+Bound (u = 2^-53 for complex128): each layer's phase sums at most
+T = n (n + 1) / 2 terms gamma_j W_ij, so it is off by at most T u gamma_j
+sum|W| (plus a rounding of gamma_j); the rotation, its product over p layers
+and the arg add a few u per layer, i.e. (4 p + 4) u rad, which is
+(4 p + 4) u / g0 in units of C.  Hence
+  |C_gpu(z) - C(z)| <= u ((T + 2) sum_{i<=j} |W_ij| + (4 p + 4) max|C|).
+complex64 rotates in FP32 (u = 2^-24 on the last two terms, after an FP64
+range reduction of the phase).  The index of the smallest C must equal the
+oracle's whenever the oracle's two smallest values differ by more than twice
+the bound; otherwise the GPU's choice must be within the bound of the
+minimum.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_10531_amd import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U64 = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def api():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2506_10531_amd import api as a
+    return a
+
+
+def cuda(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda:0")
+
+
+def folded_abs_sum(Q):
+    """sum_{i<=j} |W_ij| of the folded upper-triangular couplings."""
+    W = np.triu(Q + Q.T) - np.diag(np.diag(Q))
+    return float(np.sum(np.abs(W)))
+
+
+# whole-state launch (n <= 12), single-tile and LDS-tile passes (13), register
+# tiles over one and two qubit sets (14..24), both precisions, p = 1 and 3
+CASES = [("c128", 5, 1), ("c128", 12, 3), ("c128", 13, 1), ("c128", 16, 3),
+         ("c128", 20, 1), ("c128", 24, 3), ("c64", 9, 3), ("c64", 14, 1),
+         ("c64", 18, 3), ("c64", 22, 1), ("c64", 24, 3)]
+
+
+@pytest.mark.parametrize("prec,n,p", CASES)
+def test_cost_table_and_argmin(api, prec, n, p):
+    B = 2
+    Qs = workloads.qubos(B, n, 4100 + n)
+    Qs[1] = Qs[1] + 0.5 * np.triu(Qs[1], 1)  # one non-symmetric Q per batch
+    Cs = [oracle.cost_table(Qs[bi]) for bi in range(B)]
+    cm = np.array([float(np.max(np.abs(C))) for C in Cs])
+    w = np.array([0.5, 0.3, 0.2])[:p] if p == 3 else np.array([1.0])
+    g = (w[None, :] / cm[:, None])[:, None, :]          # [B][1][p], sums to 1 / max|C|
+    b = np.zeros_like(g)
+    print(f"cost table {prec} n={n} p={p}", flush=True)
+    psi = api.state(cuda(Qs), cuda(g), cuda(b), prec=prec)[0].cpu().numpy()[:, 0]
+    u_rot = U64 if prec == "c128" else 2.0 ** -24
+    T = n * (n + 1) // 2
+    for bi in range(B):
+        C = Cs[bi]
+        Cg = -np.angle(psi[bi].astype(np.complex128)) * cm[bi]
+        bound = U64 * (T + 2) * folded_abs_sum(Qs[bi]) + u_rot * (4 * p + 4) * cm[bi]
+        err = float(np.max(np.abs(Cg - C)))
+        print(f"  problem {bi}: max |C_gpu - C| = {err:.3e} (bound {bound:.3e})", flush=True)
+        assert err <= bound, (bi, err, bound)
+        zo = int(np.argmin(C))
+        zg = int(np.argmin(Cg))
+        two = np.partition(C, 1)[:2]
+        if two[1] - two[0] > 2.0 * bound:
+            assert zg == zo, (bi, zg, zo)
+        else:
+            assert C[zg] <= C[zo] + bound, (bi, zg, zo)
+        # the oracle's own brute-force minimiser agrees with its table
+        assert oracle.argmin(Qs[bi])[0] == zo
