@@ -4,27 +4,22 @@
 // Sec. V) hands many small sub-QUBOs to QAOA solvers and collects their
 // sub-solutions asynchronously; the paper's QFw integration submits ansatz
 // evaluations to an executor and feeds the results back to the optimiser
-// (Sec. VI).  Here one GPU serves that stream of solves:
+// (Sec. VI).  Here one GPU serves that stream of solves.  The scheduling
+// policy (FIFO admission against slots and the byte budget, steps of up to
+// MAX_EVALS_PER_STEP evaluations with two rounds in flight, the early end of
+// a step for an arrival or a cancellation, bookkeeping) is sched.h; this file
+// is its device backend and the C entry points:
 //
-//  * qaoa_submit copies a request (n, Q, initial gamma/beta, seed) into a
-//    FIFO.  A scheduler thread admits requests in FIFO order while a slot is
-//    free and the request's device bytes fit in the queue's HBM budget.
+//  * qaoa_submit copies a request (n, Q, initial gamma/beta, seed) into the
+//    FIFO; a scheduler thread admits and steps.
 //  * An admitted request keeps its Q, parameters and Adam moments in a
-//    device slot.  Every scheduler step advances all admitted requests by
-//    the same number of evaluations: the requests are grouped by qubit
-//    count, each group is gathered into a contiguous batch, and one batched
-//    adjoint pipeline (forward passes, lambda = C psi, backward passes,
-//    fixed-order reductions) plus one Adam update runs per group and
-//    evaluation, groups on separate streams.  Requests that finish their
-//    evaluations are sampled in the same step and completed.  Requests that
-//    arrive meanwhile join at the next step, so their work overlaps with the
-//    requests already running.  A step makes up to MAX_EVALS_PER_STEP
-//    evaluations, no more than any of its requests has left, enqueued round
-//    by round with at most two rounds in flight; before each further round
-//    the scheduler looks for a waiting request that a free slot and the
-//    byte budget could now take (or a cancellation), and if there is one it
-//    ends the step after the rounds already enqueued, so an arrival waits
-//    at most about two evaluations while the GPU stays busy.
+//    device slot.  In every round of a step the requests are grouped by
+//    qubit count, each group is gathered into a contiguous batch, and one
+//    batched adjoint pipeline (forward passes, lambda = C psi, backward
+//    passes, fixed-order reductions) plus one Adam update runs per group,
+//    groups on separate streams (a HIP graph per recurring group shape).
+//    Requests that finish their evaluations are sampled at the end of the
+//    step and completed.
 //  * The big buffers (checkpoints, adjoint state, probabilities) exist only
 //    within a step; a request's byte charge is what its group needs for it
 //    during a step, so the sum over admitted requests bounds the arena.
@@ -33,20 +28,18 @@
 // (n, p, precision), and every reduction sums in a fixed order, so a
 // request's result does not depend on which requests share its batch.
 #include "internal.h"
+#include "sched.h"
 #include "../../include/dqaoa.h"
 
 #include <hip/hip_runtime.h>
 #include <time.h>
 
 #include <algorithm>
-#include <condition_variable>
 #include <cstring>
-#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <thread>
-#include <unordered_map>
 #include <vector>
 
 namespace dq {
@@ -60,7 +53,6 @@ namespace {
 
 constexpr int QN_MAX = 26;      // largest sub-QUBO a request may carry
 constexpr int NSTREAMS = 4;
-constexpr int MAX_EVALS_PER_STEP = 16;
 
 int64_t now_ns() {
   timespec ts;
@@ -68,31 +60,22 @@ int64_t now_ns() {
   return (int64_t)ts.tv_sec * 1000000000ll + ts.tv_nsec;
 }
 
-struct Request {
-  uint64_t id = 0;
-  int n = 0;
+struct Request : sched::Req {
   std::vector<double> Q, g0, b0;
   uint64_t seed = 0;
-  size_t bytes = 0;
-  int state = 0;  // 0 pending, 1 active, 2 done
-  bool cancel = false;
-  bool uploaded = false;
-  int slot = -1;
-  int evals_done = 0;
-  qaoa_solve_result res{};
-  std::vector<uint64_t> samples;
 };
 
 // Per-group scratch of one step: contiguous batch arrays plus the pipelines'
 // layouts.
 struct GroupPlan {
-  int n = 0;
-  std::vector<Request*> ev, sm;  // evaluating, sampling this step
+  const sched::Group* g = nullptr;
   Layout lg, ls;
   Carve cv;
   size_t iQe = 0, iGe = 0, iBe = 0, iE = 0, iDg = 0, iDb = 0, iGrad = 0;
   size_t iQs = 0, iGs = 0, iBs = 0, iZ = 0, iBz = 0, iBc = 0, iEs = 0, iSd = 0,
          iSamp = 0;
+  size_t base = 0, res = 0;  // arena and host-result offsets
+  int ie = 0, is = 0;        // offsets of its slot lists in the index buffer
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -103,19 +86,8 @@ struct qaoa_queue {
   qaoa_ctx* ctx = nullptr;
   qaoa_queue_opts o{};
   int device = 0;
-  size_t budget = 0;
-
-  std::mutex mu;
-  std::condition_variable cv_sched, cv_done;
-  std::deque<uint64_t> pending;
-  std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
-  std::vector<Request*> slots;  // by slot index
-  std::vector<int> free_slots;
-  size_t in_use = 0;
-  uint64_t next_id = 1;
-  bool stop = false;
+  sched::Core core;
   std::thread th;
-  qaoa_queue_stats st{};
 
   // device state
   hipStream_t streams[NSTREAMS] = {};
@@ -131,6 +103,9 @@ struct qaoa_queue {
   int* hIdx = nullptr;       // [2 * slots]
   char* hRes = nullptr;      // results of one step
   size_t hRes_bytes = 0;
+  // the step in progress
+  std::vector<GroupPlan> gp;
+  int nused = 0;
 
   // Captured evaluation steps: the gather, adjoint pipeline and Adam update
   // of one n-group, replayed while the group's size and its places in the
@@ -158,26 +133,24 @@ struct qaoa_queue {
 
   size_t request_bytes(int n) const;
   void run();
-  int step();
-  int eval_group(const GroupPlan& g, const int* ie, char* base, hipStream_t s);
-  int enqueue_eval(const GroupPlan& g, const int* ie, char* base, hipStream_t s);
-  void complete(Request* r, int status);
-  bool should_yield(const std::vector<Request*>& act);
-};
+  int eval_group(const GroupPlan& g, hipStream_t s);
+  int enqueue_eval(const GroupPlan& g, hipStream_t s);
 
-// Called with the lock held: a waiting request that could be admitted right
-// now, or a cancelled request among those running, ends the step early.
-bool qaoa_queue::should_yield(const std::vector<Request*>& act) {
-  for (Request* r : act)
-    if (r->cancel) return true;
-  if (pending.empty() || free_slots.empty()) return false;
-  return in_use + reqs[pending.front()]->bytes <= budget;
-}
+  // backend of sched::run_step
+  int begin(sched::Step& s);
+  int round(int k);
+  int wait_round(int k);
+  int end(bool sampled);
+  void fetch(int gi, int i, sched::Req* r);
+  int64_t now() const { return now_ns(); }
+};
 
 // One evaluation of an n-group: gather its requests' Q and parameters,
 // the adjoint pipeline, the Adam update.  Kernels only (capturable).
-int qaoa_queue::enqueue_eval(const GroupPlan& g, const int* ie, char* base, hipStream_t s) {
-  const int n = g.n, nb = (int)g.ev.size(), p = o.p;
+int qaoa_queue::enqueue_eval(const GroupPlan& g, hipStream_t s) {
+  const int n = g.g->n, nb = (int)g.g->ev.size(), p = o.p;
+  char* base = arena + g.base;
+  const int* ie = dIdx + g.ie;
   auto A = [&](size_t i) { return base + g.cv.off[i]; };
   double *Q = (double*)A(g.iQe), *gg = (double*)A(g.iGe), *bb = (double*)A(g.iBe);
   double *E = (double*)A(g.iE), *dg = (double*)A(g.iDg), *db = (double*)A(g.iDb);
@@ -193,9 +166,9 @@ int qaoa_queue::enqueue_eval(const GroupPlan& g, const int* ie, char* base, hipS
 
 // The group's evaluation as a graph replay when its shape recurs, captured
 // on first use; eager when graphs are off.
-int qaoa_queue::eval_group(const GroupPlan& g, const int* ie, char* base, hipStream_t s) {
-  if (!use_graphs) return enqueue_eval(g, ie, base, s);
-  const GraphKey key{g.n, (int)g.ev.size(), base, ie};
+int qaoa_queue::eval_group(const GroupPlan& g, hipStream_t s) {
+  if (!use_graphs) return enqueue_eval(g, s);
+  const GraphKey key{g.g->n, (int)g.g->ev.size(), arena + g.base, dIdx + g.ie};
   auto it = graphs.find(key);
   if (it == graphs.end()) {
     if (graphs.size() >= 256) {  // evict the least recently used (not in flight:
@@ -207,7 +180,7 @@ int qaoa_queue::eval_group(const GroupPlan& g, const int* ie, char* base, hipStr
     }
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");
-    int rc = enqueue_eval(g, ie, base, s);
+    int rc = enqueue_eval(g, s);
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(s, &graph);
     if (rc || e2 != hipSuccess) {
@@ -238,51 +211,15 @@ size_t qaoa_queue::request_bytes(int n) const {
   return lg.cv.total + ls.cv.total + arrays + 4096;
 }
 
-void qaoa_queue::complete(Request* r, int status) {
-  r->res.status = status;
-  r->res.n = r->n;
-  r->res.t_done_ns = now_ns();
-  if (r->state == 1) {
-    in_use -= r->bytes;
-    slots[r->slot] = nullptr;
-    free_slots.push_back(r->slot);
-    r->slot = -1;
-  }
-  r->state = 2;
-  if (status == QAOA_OK) st.completed++;
-  else if (status == QAOA_ERR_CANCELLED) st.cancelled++;
-  cv_done.notify_all();
-}
-
-// One scheduler step over all admitted requests.  Called without the lock
-// held; takes it for bookkeeping only.
-int qaoa_queue::step() {
+// Start of a step: upload the newly admitted requests (Q, gamma0, beta0,
+// seed; zero Adam state), the groups' slot lists, and carve every group's
+// batch arrays and pipeline scratch out of the arena.
+int qaoa_queue::begin(sched::Step& s) {
   ++step_no;
-  std::vector<Request*> act, fresh;
-  {
-    std::lock_guard<std::mutex> lk(mu);
-    for (Request* r : slots)
-      if (r) {
-        if (r->cancel) continue;
-        act.push_back(r);
-        if (!r->uploaded) fresh.push_back(r);
-      }
-  }
-  if (act.empty()) return QAOA_OK;
-  // evaluations per request this step (fewer if an arrival ends it early)
-  int K = MAX_EVALS_PER_STEP;
-  bool evaluating = false;
-  for (Request* r : act)
-    if (r->evals_done < o.evals) {
-      K = std::min(K, o.evals - r->evals_done);
-      evaluating = true;
-    }
-  if (!evaluating) K = 1;
   const int p = o.p;
   hipStream_t s0 = streams[0];
-  // upload newly admitted requests: Q, gamma0, beta0; zero Adam state
-  for (size_t i = 0; i < fresh.size(); ++i) {
-    Request* r = fresh[i];
+  for (size_t i = 0; i < s.fresh.size(); ++i) {
+    const Request* r = static_cast<const Request*>(s.fresh[i]);
     double* h = hUp + i * (QN_MAX * QN_MAX + 2 * p + 1);
     std::memcpy(h, r->Q.data(), sizeof(double) * r->n * r->n);
     std::memcpy(h + QN_MAX * QN_MAX, r->g0.data(), sizeof(double) * p);
@@ -304,30 +241,17 @@ int qaoa_queue::step() {
     if (e == hipSuccess) e = hipMemsetAsync(dV + (size_t)sl * 2 * p, 0, sizeof(double) * 2 * p, s0);
     if (e == hipSuccess) e = hipMemsetAsync(dT + sl, 0, sizeof(int), s0);
     if (e != hipSuccess) return hip_error(e, "queue upload");
-    r->uploaded = true;
   }
-  // groups by n
-  std::map<int, GroupPlan> groups;
-  for (Request* r : act) {
-    GroupPlan& g = groups[r->n];
-    g.n = r->n;
-    if (r->evals_done < o.evals) {
-      g.ev.push_back(r);
-      if (r->evals_done + K == o.evals) g.sm.push_back(r);
-    } else {
-      g.sm.push_back(r);
-    }
-  }
-  // index lists
-  int nidx = 0;
-  std::vector<std::pair<int, int>> idx_off;  // per group: ev offset, sm offset
-  for (auto& kv : groups) {
-    GroupPlan& g = kv.second;
-    const int a = nidx;
-    for (Request* r : g.ev) hIdx[nidx++] = r->slot;
-    const int b = nidx;
-    for (Request* r : g.sm) hIdx[nidx++] = r->slot;
-    idx_off.push_back({a, b});
+  // slot lists: per group, the evaluated then the sampled requests
+  gp.assign(s.groups.size(), GroupPlan());
+  int nidx = 0, gi = 0;
+  for (auto& kv : s.groups) {
+    GroupPlan& g = gp[gi++];
+    g.g = &kv.second;
+    g.ie = nidx;
+    for (const sched::Req* r : g.g->ev) hIdx[nidx++] = r->slot;
+    g.is = nidx;
+    for (const sched::Req* r : g.g->sm) hIdx[nidx++] = r->slot;
   }
   hipError_t e = hipMemcpyAsync(dIdx, hIdx, sizeof(int) * nidx, hipMemcpyHostToDevice, s0);
   if (e != hipSuccess) return hip_error(e, "queue index upload");
@@ -335,11 +259,8 @@ int qaoa_queue::step() {
   if (e != hipSuccess) return hip_error(e, "hipEventRecord");
   // plan and carve every group
   size_t off = 0, res_off = 0;
-  int gi = 0;
-  std::vector<size_t> g_base, g_res;
-  for (auto& kv : groups) {
-    GroupPlan& g = kv.second;
-    const int n = g.n, nb = (int)g.ev.size(), ns = (int)g.sm.size();
+  for (GroupPlan& g : gp) {
+    const int n = g.g->n, nb = (int)g.g->ev.size(), ns = (int)g.g->sm.size();
     if (nb) {
       int rc = make_layout(OP_GRAD, o.prec, nb, n, p, 1, 0, &g.lg);
       if (rc) return rc;
@@ -364,176 +285,134 @@ int qaoa_queue::step() {
       g.iSd = g.cv.add((size_t)ns * 8);
       g.iSamp = g.cv.add(g.ls.cv.total);
     }
-    g_base.push_back(off);
+    g.base = off;
     off += align256(g.cv.total);
-    g_res.push_back(res_off);
+    g.res = res_off;
     res_off += (size_t)ns * (o.shots + 2 * p + 3) * 8;
-    ++gi;
   }
-  if (off > budget)
-    return set_error(QAOA_ERR_OUT_OF_MEMORY, "step needs %zu arena bytes of %zu", off, budget);
+  if (off > core.budget)
+    return set_error(QAOA_ERR_OUT_OF_MEMORY, "step needs %zu arena bytes of %zu", off,
+                     core.budget);
   if (res_off > hRes_bytes)
     return set_error(QAOA_ERR_OUT_OF_MEMORY, "step results exceed the staging buffer");
-  // evaluation rounds: round k enqueues one evaluation of every group on the
-  // group's stream; from the third round (k = 2) on, the host first waits
-  // for round k - 2 and ends the step there if a waiting request could now
-  // be admitted
-  gi = 0;
-  for (auto& kv : groups) {
-    hipStream_t s = streams[gi % NSTREAMS];
-    (void)kv;
-    if (s != s0) {
-      e = hipStreamWaitEvent(s, ev_up, 0);
+  // every group's stream starts after the uploads
+  for (size_t i = 0; i < gp.size(); ++i) {
+    hipStream_t st = streams[i % NSTREAMS];
+    if (st != s0) {
+      e = hipStreamWaitEvent(st, ev_up, 0);
       if (e != hipSuccess) return hip_error(e, "hipStreamWaitEvent");
     }
-    ++gi;
   }
-  const int nused = std::min<int>((int)groups.size(), NSTREAMS);
-  int Kdone = K;
-  for (int k = 0; k < K; ++k) {
-    if (k >= 2) {
-      for (int i = 0; i < nused; ++i) {
-        e = hipEventSynchronize(ev_round[k % 2][i]);
-        if (e != hipSuccess) return hip_error(e, "hipEventSynchronize");
-      }
-      std::lock_guard<std::mutex> lk(mu);
-      if (should_yield(act)) {
-        Kdone = k;
-        break;
-      }
-    }
-    gi = 0;
-    for (auto& kv : groups) {
-      GroupPlan& g = kv.second;
-      if (!g.ev.empty()) {
-        int rc = eval_group(g, dIdx + idx_off[gi].first, arena + g_base[gi],
-                            streams[gi % NSTREAMS]);
-        if (rc) return rc;
-      }
-      ++gi;
-    }
-    for (int i = 0; i < nused; ++i) {
-      e = hipEventRecord(ev_round[k % 2][i], streams[i]);
-      if (e != hipSuccess) return hip_error(e, "hipEventRecord");
-    }
+  nused = std::min<int>((int)gp.size(), NSTREAMS);
+  return QAOA_OK;
+}
+
+// Round k: one evaluation of every group on the group's stream; the round's
+// end is recorded per stream (two rounds' events are kept).
+int qaoa_queue::round(int k) {
+  for (size_t gi = 0; gi < gp.size(); ++gi) {
+    if (gp[gi].g->ev.empty()) continue;
+    int rc = eval_group(gp[gi], streams[gi % NSTREAMS]);
+    if (rc) return rc;
   }
-  // requests reach their last evaluation only when the step ran all K rounds
-  // (K is the fewest evaluations any request has left)
-  const bool sampled = Kdone == K;
-  gi = 0;
-  for (auto& kv : groups) {
-    GroupPlan& g = kv.second;
+  for (int i = 0; i < nused; ++i) {
+    hipError_t e = hipEventRecord(ev_round[k % 2][i], streams[i]);
+    if (e != hipSuccess) return hip_error(e, "hipEventRecord");
+  }
+  return QAOA_OK;
+}
+
+int qaoa_queue::wait_round(int k) {
+  for (int i = 0; i < nused; ++i) {
+    hipError_t e = hipEventSynchronize(ev_round[k % 2][i]);
+    if (e != hipSuccess) return hip_error(e, "hipEventSynchronize");
+  }
+  return QAOA_OK;
+}
+
+// End of a step: sample every group's finished requests at their final
+// parameters and copy the results to the host, then drain the streams.
+int qaoa_queue::end(bool sampled) {
+  const int p = o.p;
+  for (size_t gi = 0; gi < gp.size() && sampled; ++gi) {
+    const GroupPlan& g = gp[gi];
+    const int n = g.g->n, ns = (int)g.g->sm.size();
+    if (!ns) continue;
     hipStream_t s = streams[gi % NSTREAMS];
-    char* base = arena + g_base[gi];
-    const int n = g.n, ns = sampled ? (int)g.sm.size() : 0;
-    const int* is = dIdx + idx_off[gi].second;
+    char* base = arena + g.base;
     auto A = [&](size_t i) { return base + g.cv.off[i]; };
-    if (ns) {
-      double *Q = (double*)A(g.iQs), *gg = (double*)A(g.iGs), *bb = (double*)A(g.iBs);
-      uint64_t* z = (uint64_t*)A(g.iZ);
-      uint64_t* bz = (uint64_t*)A(g.iBz);
-      double *bc = (double*)A(g.iBc), *es = (double*)A(g.iEs);
-      uint64_t* sd = (uint64_t*)A(g.iSd);
-      e = launch_gather(ns, n, p, is, dQ, QN_MAX * QN_MAX, dG, dB, dSeed, Q, gg, bb, sd, s);
-      if (e != hipSuccess) return hip_error(e, "gather");
-      int rc = enqueue_sample(g.ls, A(g.iSamp), Q, gg, bb, o.shots, 0, sd, z, nullptr, bz,
-                              bc, es, s, nullptr);
-      if (rc) return rc;
-      char* hr = hRes + g_res[gi];
-      e = hipMemcpyAsync(hr, z, (size_t)ns * o.shots * 8, hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(hr + (size_t)ns * o.shots * 8, gg, (size_t)ns * p * 8,
-                           hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(hr + (size_t)ns * (o.shots + p) * 8, bb, (size_t)ns * p * 8,
-                           hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(hr + (size_t)ns * (o.shots + 2 * p) * 8, bz, (size_t)ns * 8,
-                           hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(hr + (size_t)ns * (o.shots + 2 * p + 1) * 8, bc, (size_t)ns * 8,
-                           hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(hr + (size_t)ns * (o.shots + 2 * p + 2) * 8, es, (size_t)ns * 8,
-                           hipMemcpyDeviceToHost, s);
-      if (e != hipSuccess) return hip_error(e, "result copy");
-    }
-    ++gi;
+    double *Q = (double*)A(g.iQs), *gg = (double*)A(g.iGs), *bb = (double*)A(g.iBs);
+    uint64_t* z = (uint64_t*)A(g.iZ);
+    uint64_t* bz = (uint64_t*)A(g.iBz);
+    double *bc = (double*)A(g.iBc), *es = (double*)A(g.iEs);
+    uint64_t* sd = (uint64_t*)A(g.iSd);
+    hipError_t e = launch_gather(ns, n, p, dIdx + g.is, dQ, QN_MAX * QN_MAX, dG, dB, dSeed, Q,
+                                 gg, bb, sd, s);
+    if (e != hipSuccess) return hip_error(e, "gather");
+    int rc = enqueue_sample(g.ls, A(g.iSamp), Q, gg, bb, o.shots, 0, sd, z, nullptr, bz, bc, es,
+                            s, nullptr);
+    if (rc) return rc;
+    char* hr = hRes + g.res;
+    e = hipMemcpyAsync(hr, z, (size_t)ns * o.shots * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hr + (size_t)ns * o.shots * 8, gg, (size_t)ns * p * 8,
+                         hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hr + (size_t)ns * (o.shots + p) * 8, bb, (size_t)ns * p * 8,
+                         hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hr + (size_t)ns * (o.shots + 2 * p) * 8, bz, (size_t)ns * 8,
+                         hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hr + (size_t)ns * (o.shots + 2 * p + 1) * 8, bc, (size_t)ns * 8,
+                         hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hr + (size_t)ns * (o.shots + 2 * p + 2) * 8, es, (size_t)ns * 8,
+                         hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_error(e, "result copy");
   }
   for (int i = 0; i < NSTREAMS; ++i) {
-    e = hipStreamSynchronize(streams[i]);
+    hipError_t e = hipStreamSynchronize(streams[i]);
     if (e != hipSuccess) return hip_error(e, "hipStreamSynchronize");
   }
-  // bookkeeping
-  std::lock_guard<std::mutex> lk(mu);
-  gi = 0;
-  for (auto& kv : groups) {
-    GroupPlan& g = kv.second;
-    for (Request* r : g.ev) r->evals_done += Kdone;
-    const int ns = sampled ? (int)g.sm.size() : 0;
-    const char* hr = hRes + g_res[gi];
-    for (int i = 0; i < ns; ++i) {
-      Request* r = g.sm[i];
-      const uint64_t* z = (const uint64_t*)hr;
-      const double* gg = (const double*)(hr + (size_t)ns * o.shots * 8);
-      const double* bb = (const double*)(hr + (size_t)ns * (o.shots + p) * 8);
-      const uint64_t* bz = (const uint64_t*)(hr + (size_t)ns * (o.shots + 2 * p) * 8);
-      const double* bc = (const double*)(hr + (size_t)ns * (o.shots + 2 * p + 1) * 8);
-      const double* es = (const double*)(hr + (size_t)ns * (o.shots + 2 * p + 2) * 8);
-      r->samples.assign(z + (size_t)i * o.shots, z + (size_t)(i + 1) * o.shots);
-      for (int j = 0; j < p; ++j) {
-        r->res.gamma[j] = gg[i * p + j];
-        r->res.beta[j] = bb[i * p + j];
-      }
-      r->res.best_z = bz[i];
-      r->res.best_c = bc[i];
-      r->res.expect = es[i];
-      complete(r, QAOA_OK);
-    }
-    ++gi;
-  }
-  st.steps++;
   return QAOA_OK;
+}
+
+void qaoa_queue::fetch(int gi, int i, sched::Req* r) {
+  const int p = o.p, ns = (int)gp[gi].g->sm.size();
+  const char* hr = hRes + gp[gi].res;
+  const uint64_t* z = (const uint64_t*)hr;
+  const double* gg = (const double*)(hr + (size_t)ns * o.shots * 8);
+  const double* bb = (const double*)(hr + (size_t)ns * (o.shots + p) * 8);
+  const uint64_t* bz = (const uint64_t*)(hr + (size_t)ns * (o.shots + 2 * p) * 8);
+  const double* bc = (const double*)(hr + (size_t)ns * (o.shots + 2 * p + 1) * 8);
+  const double* es = (const double*)(hr + (size_t)ns * (o.shots + 2 * p + 2) * 8);
+  r->samples.assign(z + (size_t)i * o.shots, z + (size_t)(i + 1) * o.shots);
+  for (int j = 0; j < p; ++j) {
+    r->res.gamma[j] = gg[i * p + j];
+    r->res.beta[j] = bb[i * p + j];
+  }
+  r->res.best_z = bz[i];
+  r->res.best_c = bc[i];
+  r->res.expect = es[i];
 }
 
 void qaoa_queue::run() {
   (void)hipSetDevice(device);
   for (;;) {
     {
-      std::unique_lock<std::mutex> lk(mu);
+      std::unique_lock<std::mutex> lk(core.mu);
       for (;;) {
-        // cancellations of admitted requests take effect between steps
-        for (Request* r : slots)
-          if (r && r->cancel) complete(r, QAOA_ERR_CANCELLED);
-        // FIFO admission against free slots and the byte budget
-        while (!pending.empty() && !free_slots.empty()) {
-          Request* r = reqs[pending.front()].get();
-          if (in_use + r->bytes > budget) break;
-          pending.pop_front();
-          r->slot = free_slots.back();
-          free_slots.pop_back();
-          slots[r->slot] = r;
-          in_use += r->bytes;
-          r->state = 1;
-          r->res.t_admit_ns = now_ns();
-          st.admitted++;
-        }
-        int resident = 0;
-        for (Request* r : slots) resident += r != nullptr;
-        st.peak_active = std::max(st.peak_active, resident);
-        st.peak_bytes = std::max(st.peak_bytes, in_use);
-        const bool any = resident > 0;
-        if (stop) return;
-        if (any) break;
-        cv_sched.wait(lk);
+        const int resident = core.admit(now_ns());
+        if (core.stop) return;
+        if (resident) break;
+        core.cv_sched.wait(lk);
       }
     }
-    int rc = step();
-    if (rc != QAOA_OK) {
+    if (sched::run_step(core, *this) != QAOA_OK) {
       // fail every admitted request of this step; keep serving the rest
-      std::lock_guard<std::mutex> lk(mu);
-      for (Request* r : slots)
-        if (r) complete(r, QAOA_ERR_HIP);
+      std::lock_guard<std::mutex> lk(core.mu);
+      core.fail_active(QAOA_ERR_HIP, now_ns());
       for (int i = 0; i < NSTREAMS; ++i) (void)hipStreamSynchronize(streams[i]);
       (void)hipGetLastError();
     }
@@ -572,12 +451,13 @@ int qaoa_queue_create(qaoa_ctx* ctx, const qaoa_queue_opts* opts, qaoa_queue** o
   }
   const int S = q->o.max_slots, p = o.p;
   if (hipSetDevice(dev) != hipSuccess) return set_error(QAOA_ERR_HIP, "hipSetDevice");
-  q->budget = o.hbm_budget;
-  if (!q->budget) {  // half the context's budget, within what is free right now
+  size_t budget = o.hbm_budget;
+  if (!budget) {  // half the context's budget, within what is free right now
     size_t fr = 0, tot = 0;
-    q->budget = ctx_budget(ctx) / 2;
-    if (hipMemGetInfo(&fr, &tot) == hipSuccess) q->budget = std::min(q->budget, fr / 10 * 8);
+    budget = ctx_budget(ctx) / 2;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) budget = std::min(budget, fr / 10 * 8);
   }
+  q->core.init(S, o.max_pending, budget, o.evals);
   hipError_t e = hipSuccess;
   for (int i = 0; i < NSTREAMS && e == hipSuccess; ++i)
     e = hipStreamCreateWithFlags(&q->streams[i], hipStreamNonBlocking);
@@ -585,7 +465,7 @@ int qaoa_queue_create(qaoa_ctx* ctx, const qaoa_queue_opts* opts, qaoa_queue** o
   for (int r = 0; r < 2; ++r)
     for (int i = 0; i < NSTREAMS && e == hipSuccess; ++i)
       e = hipEventCreateWithFlags(&q->ev_round[r][i], hipEventDisableTiming);
-  if (e == hipSuccess) e = hipMalloc((void**)&q->arena, q->budget);
+  if (e == hipSuccess) e = hipMalloc((void**)&q->arena, budget);
   if (e == hipSuccess) e = hipMalloc((void**)&q->dQ, sizeof(double) * S * QN_MAX * QN_MAX);
   if (e == hipSuccess) e = hipMalloc((void**)&q->dG, sizeof(double) * S * p);
   if (e == hipSuccess) e = hipMalloc((void**)&q->dB, sizeof(double) * S * p);
@@ -606,8 +486,6 @@ int qaoa_queue_create(qaoa_ctx* ctx, const qaoa_queue_opts* opts, qaoa_queue** o
     return set_error(e == hipErrorOutOfMemory ? QAOA_ERR_OUT_OF_MEMORY : QAOA_ERR_HIP,
                      "queue allocation: %s", hipGetErrorString(e));
   }
-  q->slots.assign(S, nullptr);
-  for (int i = S - 1; i >= 0; --i) q->free_slots.push_back(i);
   qaoa_queue* qq = q.release();
   qq->th = std::thread([qq] { qq->run(); });
   *out = qq;
@@ -617,10 +495,10 @@ int qaoa_queue_create(qaoa_ctx* ctx, const qaoa_queue_opts* opts, qaoa_queue** o
 int qaoa_queue_destroy(qaoa_queue* q) {
   if (!q) return set_error(QAOA_ERR_INVALID_ARG, "queue is NULL");
   {
-    std::lock_guard<std::mutex> lk(q->mu);
-    q->stop = true;
+    std::lock_guard<std::mutex> lk(q->core.mu);
+    q->core.stop = true;
   }
-  q->cv_sched.notify_all();
+  q->core.cv_sched.notify_all();
   if (q->th.joinable()) q->th.join();
   (void)hipSetDevice(q->device);
   for (int i = 0; i < NSTREAMS; ++i)
@@ -657,59 +535,38 @@ int qaoa_submit(qaoa_queue* q, const qaoa_solve_req* req, uint64_t* ticket) {
   r->b0.assign(req->beta0, req->beta0 + q->o.p);
   r->seed = req->seed;
   r->bytes = bytes;
-  std::lock_guard<std::mutex> lk(q->mu);
-  if (bytes > q->budget) {
-    q->st.rejected++;
-    return set_error(QAOA_ERR_OUT_OF_MEMORY,
-                     "a %d-qubit request needs %zu bytes; the queue budget is %zu", req->n,
-                     bytes, q->budget);
-  }
-  if ((int)q->pending.size() >= q->o.max_pending) {
-    q->st.rejected++;
-    return set_error(QAOA_ERR_QUEUE_FULL, "%zu requests pending", q->pending.size());
-  }
-  r->id = q->next_id++;
-  r->res.t_submit_ns = now_ns();
-  r->res.status = QAOA_PENDING;
-  *ticket = r->id;
-  q->pending.push_back(r->id);
-  q->reqs[r->id] = std::move(r);
-  q->st.submitted++;
-  q->cv_sched.notify_all();
-  return QAOA_OK;
+  std::lock_guard<std::mutex> lk(q->core.mu);
+  const int rc = q->core.submit(std::move(r), now_ns(), ticket);
+  if (rc == QAOA_ERR_OUT_OF_MEMORY)
+    return set_error(rc, "a %d-qubit request needs %zu bytes; the queue budget is %zu", req->n,
+                     bytes, q->core.budget);
+  if (rc == QAOA_ERR_QUEUE_FULL)
+    return set_error(rc, "%zu requests pending", q->core.pending.size());
+  return rc;
 }
 
 static int take_result(qaoa_queue* q, uint64_t ticket, qaoa_solve_result* out,
                        uint64_t* samples) {
-  auto it = q->reqs.find(ticket);
-  if (it == q->reqs.end()) return set_error(QAOA_ERR_NOT_FOUND, "unknown ticket %llu",
-                                            (unsigned long long)ticket);
-  Request* r = it->second.get();
-  if (r->state != 2) return QAOA_PENDING;
-  if (out) *out = r->res;
-  if (samples && !r->samples.empty())
-    std::memcpy(samples, r->samples.data(), r->samples.size() * sizeof(uint64_t));
-  q->reqs.erase(it);
-  return QAOA_OK;
+  const int rc = q->core.take(ticket, out, samples);
+  if (rc == QAOA_ERR_NOT_FOUND)
+    return set_error(rc, "unknown ticket %llu", (unsigned long long)ticket);
+  return rc;
 }
 
 int qaoa_poll(qaoa_queue* q, uint64_t ticket, qaoa_solve_result* out, uint64_t* samples) {
   if (!q) return set_error(QAOA_ERR_INVALID_ARG, "queue is NULL");
-  std::lock_guard<std::mutex> lk(q->mu);
+  std::lock_guard<std::mutex> lk(q->core.mu);
   return take_result(q, ticket, out, samples);
 }
 
 int qaoa_wait(qaoa_queue* q, uint64_t ticket, int64_t timeout_ns, qaoa_solve_result* out,
               uint64_t* samples) {
   if (!q) return set_error(QAOA_ERR_INVALID_ARG, "queue is NULL");
-  std::unique_lock<std::mutex> lk(q->mu);
-  auto ready = [&] {
-    auto it = q->reqs.find(ticket);
-    return it == q->reqs.end() || it->second->state == 2;
-  };
+  std::unique_lock<std::mutex> lk(q->core.mu);
+  auto ready = [&] { return q->core.finished(ticket); };
   if (timeout_ns < 0) {
-    q->cv_done.wait(lk, ready);
-  } else if (!q->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), ready)) {
+    q->core.cv_done.wait(lk, ready);
+  } else if (!q->core.cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), ready)) {
     return set_error(QAOA_ERR_TIMEOUT, "ticket %llu not done", (unsigned long long)ticket);
   }
   return take_result(q, ticket, out, samples);
@@ -717,31 +574,17 @@ int qaoa_wait(qaoa_queue* q, uint64_t ticket, int64_t timeout_ns, qaoa_solve_res
 
 int qaoa_cancel(qaoa_queue* q, uint64_t ticket) {
   if (!q) return set_error(QAOA_ERR_INVALID_ARG, "queue is NULL");
-  std::lock_guard<std::mutex> lk(q->mu);
-  auto it = q->reqs.find(ticket);
-  if (it == q->reqs.end() || it->second->state == 2)
-    return set_error(QAOA_ERR_NOT_FOUND, "ticket %llu unknown or finished",
-                     (unsigned long long)ticket);
-  Request* r = it->second.get();
-  if (r->state == 0) {
-    q->pending.erase(std::find(q->pending.begin(), q->pending.end(), ticket));
-    q->complete(r, QAOA_ERR_CANCELLED);
-  } else {
-    r->cancel = true;
-    q->cv_sched.notify_all();
-  }
-  return QAOA_OK;
+  std::lock_guard<std::mutex> lk(q->core.mu);
+  const int rc = q->core.cancel(ticket, now_ns());
+  if (rc == QAOA_ERR_NOT_FOUND)
+    return set_error(rc, "ticket %llu unknown or finished", (unsigned long long)ticket);
+  return rc;
 }
 
 int qaoa_queue_get_stats(qaoa_queue* q, qaoa_queue_stats* out) {
   if (!q || !out) return set_error(QAOA_ERR_INVALID_ARG, "NULL argument");
-  std::lock_guard<std::mutex> lk(q->mu);
-  *out = q->st;
-  out->pending = (int)q->pending.size();
-  int act = 0;
-  for (Request* r : q->slots) act += r != nullptr;
-  out->active = act;
-  out->bytes_in_use = q->in_use;
+  std::lock_guard<std::mutex> lk(q->core.mu);
+  *out = q->core.stats();
   return QAOA_OK;
 }
 
