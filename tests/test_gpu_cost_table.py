@@ -48,10 +48,11 @@ def folded_abs_sum(Q):
 
 
 # whole-state launch (n <= 12), single-tile and LDS-tile passes (13), register
-# tiles over one and two qubit sets (14..24), both precisions, p = 1 and 3
+# tiles over one and two qubit sets (14..24) and three sets with lead-only
+# passes (25, 26), both precisions, p = 1 and 3
 CASES = [("c128", 5, 1), ("c128", 12, 3), ("c128", 13, 1), ("c128", 16, 3),
-         ("c128", 20, 1), ("c128", 24, 3), ("c64", 9, 3), ("c64", 14, 1),
-         ("c64", 18, 3), ("c64", 22, 1), ("c64", 24, 3)]
+         ("c128", 20, 1), ("c128", 24, 3), ("c128", 25, 3), ("c64", 9, 3), ("c64", 14, 1),
+         ("c64", 18, 3), ("c64", 22, 1), ("c64", 24, 3), ("c64", 26, 3)]
 
 
 @pytest.mark.parametrize("prec,n,p", CASES)
@@ -82,5 +83,5 @@ def test_cost_table_and_argmin(api, prec, n, p):
             assert zg == zo, (bi, zg, zo)
         else:
             assert C[zg] <= C[zo] + bound, (bi, zg, zo)
-        # the oracle's own brute-force minimiser agrees with its table
-        assert oracle.argmin(Qs[bi])[0] == zo
+        if n <= 24:  # the oracle's own brute-force minimiser agrees with its table
+            assert oracle.argmin(Qs[bi])[0] == zo
