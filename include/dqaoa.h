@@ -147,9 +147,9 @@ int qaoa_sample(qaoa_ctx* ctx, int prec, int B, int n, int p,
  *   d<C>/dbeta_j  = -2 Im sum_q <lambda_j|X_q|psi_j>,
  *   d<C>/dgamma_j =  2 Im <lambda'_j|C|psi'_j>  (psi', lambda' after undoing
  *                                                 the mixer of layer j).
- * States of n <= 12 qubits run in one launch with psi and lambda in
- * registers and use no scratch; larger states keep per-pass checkpoints of
- * psi in the context's scratch (charged to the budget).
+ * States of up to 13 (C64) or 12 (C128) qubits run in one launch with psi
+ * and lambda in registers and use no scratch; larger states keep per-pass
+ * checkpoints of psi in the context's scratch (charged to the budget).
  *   Q [B][n][n]; gammas, betas [B][S][p] (in).
  *   expect [B][S] out (nullable); dgamma, dbeta [B][S][p] out.
  * Errors as qaoa_expect. */
@@ -178,9 +178,10 @@ int qaoa_plan(qaoa_ctx* ctx, int prec, int B, int n, int p, int S, int grad,
  * {set, tile_qubits k, contiguous low qubits c, first high tile bit a,
  *  first mixed tile qubit, lead layer (-1: none), first phase layer,
  *  last phase layer (first > last: none), flags, kernel (0: LDS tile,
- *  1/2: register tile, set 0 / the other sets)}.  (qaoa_expect, qaoa_state
- *  and qaoa_grad run states of n <= 12 in one whole-state launch instead of
- *  the single pass listed.)  A pass applies the mixer
+ *  1/2: register tile, set 0 / the other sets)}.  (qaoa_expect and
+ *  qaoa_state run states of up to 14 (C64) or 13 (C128) qubits, qaoa_grad
+ *  up to 13 or 12, in one whole-state launch instead of the single pass
+ *  listed.)  A pass applies the mixer
  * of the lead layer to its set, then for each phase layer j the phase of
  * layer j and the mixer of layer j on its set.  Tile qubits are global bits
  * [0, c) and [a, a + k - c) (all of [0, k) when c == k); the mixed tile

@@ -306,7 +306,7 @@ static bool grad_reg_off() {
 // selects the LDS-tile adjoint instead.
 // Whole-state adjoint (small.hip) for n up to this size; DQAOA_GRAD_KERNEL=lds
 // selects the LDS-tile adjoint instead.
-static int small_grad_nmax() { return grad_reg_off() ? 0 : SMALL_NMAX; }
+static int small_grad_limit(int prec) { return grad_reg_off() ? 0 : small_grad_nmax(prec); }
 
 static bool use_reg13(int op, int prec, int n) {
   return !grad_reg_off() && op == OP_GRAD && prec == QAOA_C64 && n >= 14 && n <= 22;
@@ -483,7 +483,7 @@ int enqueue_expect(const Layout& L, char* base, const double* Q,
                    const double* gammas, const double* betas, double* expect,
                    double* norm, void* probs, void* psi, hipStream_t s,
                    PassTimer* tm) {
-  if (L.plan.npass == 1 && L.n <= SMALL_NMAX && !fwd_reg_off()) {
+  if (L.plan.npass == 1 && L.n <= small_fwd_nmax(L.prec) && !fwd_reg_off()) {
     // the whole state in one work-group's registers: one launch, no scratch
     const double out = (double)L.state_bytes * L.nstates * ((probs ? 0.5 : 0.0) + (psi ? 1.0 : 0.0));
     TimerScope ts(tm, s, out);
@@ -528,7 +528,7 @@ int enqueue_sample(const Layout& L, char* base, const double* Q,
 int enqueue_grad(const Layout& L, char* base, const double* Q,
                  const double* gammas, const double* betas, double* expect,
                  double* dgamma, double* dbeta, hipStream_t s, PassTimer* tm) {
-  if (L.n <= small_grad_nmax()) {
+  if (L.n <= small_grad_limit(L.prec)) {
     // psi and lambda of the whole state in one work-group's registers
     TimerScope ts(tm, s, 0.0);
     hipError_t e = launch_small_grad(L.prec, L.n, L.p, L.S, (int)L.nstates, Q, gammas, betas,
@@ -936,7 +936,7 @@ int qaoa_expect(qaoa_ctx* ctx, int prec, int B, int n, int p, int S,
   if (rc) return rc;
   if (!Q || !gammas || !betas || !expect)
     return set_error(QAOA_ERR_INVALID_ARG, "Q, gammas, betas and expect must be non-NULL");
-  if (n <= SMALL_NMAX && !fwd_reg_off()) {
+  if (n <= small_fwd_nmax(prec) && !fwd_reg_off()) {
     // the whole state in one work-group's registers: no plan and no scratch
     if (ctx->device < 0) return set_error(QAOA_ERR_NO_DEVICE, "host-only context");
     DeviceGuard g(ctx->device);
@@ -1043,7 +1043,7 @@ int qaoa_grad(qaoa_ctx* ctx, int prec, int B, int n, int p, int S,
   if (rc) return rc;
   if (!Q || !gammas || !betas || !dgamma || !dbeta)
     return set_error(QAOA_ERR_INVALID_ARG, "Q, gammas, betas, dgamma and dbeta must be non-NULL");
-  if (n <= small_grad_nmax()) {
+  if (n <= small_grad_limit(prec)) {
     // the whole state in one work-group's registers: no plan and no scratch
     if (ctx->device < 0) return set_error(QAOA_ERR_NO_DEVICE, "host-only context");
     DeviceGuard g(ctx->device);

@@ -190,10 +190,12 @@ hipError_t launch_prep(int nprob, int n, const double* Q, double* W,
                        const double* betas, LayerCoef* coef,
                        hipStream_t stream);
 
-// Whole-state evaluation for n <= SMALL_NMAX (small.hip): the fold of Q, the
-// p layers, <C> and the norm, and the optional probabilities and state, in
-// one launch of one work-group per state.
-constexpr int SMALL_NMAX = 12;
+// Whole-state evaluation (small.hip): the fold of Q, the p layers, <C> and
+// the norm, and the optional probabilities and state, in one launch of one
+// work-group per state, for n up to small_fwd_nmax(prec); the adjoint
+// gradient likewise up to small_grad_nmax(prec) (prec as QAOA_C64 / C128).
+inline int small_fwd_nmax(int prec) { return prec == 1 ? 14 : 13; }
+inline int small_grad_nmax(int prec) { return prec == 1 ? 13 : 12; }
 hipError_t launch_small_expect(int prec, int n, int p, int S, int nstates, const double* Q,
                                const double* gammas, const double* betas, double* expect,
                                double* norm, void* probs, void* psi, hipStream_t stream);

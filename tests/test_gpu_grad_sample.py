@@ -45,7 +45,7 @@ GRAD_CASES = [("c128", 1, 2), ("c128", 3, 1), ("c128", 7, 2), ("c128", 8, 3), ("
               ("c128", 10, 3), ("c128", 11, 2), ("c128", 12, 2), ("c128", 13, 2),
               ("c128", 14, 1), ("c128", 16, 3), ("c128", 17, 4), ("c128", 18, 2),
               ("c128", 20, 6), ("c128", 22, 2), ("c64", 2, 3), ("c64", 5, 2), ("c64", 7, 1),
-              ("c64", 9, 3), ("c64", 10, 2), ("c64", 11, 3), ("c64", 12, 4), ("c64", 13, 4),
+              ("c64", 9, 3), ("c64", 10, 2), ("c64", 11, 3), ("c64", 12, 4), ("c64", 13, 1), ("c64", 13, 4),
               ("c64", 14, 2), ("c64", 15, 1), ("c64", 16, 6), ("c64", 17, 5),
               ("c64", 18, 3), ("c64", 19, 3), ("c64", 20, 2), ("c64", 21, 1),
               ("c64", 22, 2)]

@@ -75,6 +75,28 @@ def test_multipass_state_and_expect(api, n, p, prec):
     run_case(api, n, p, S=2, prec=prec, B=2 if n < 20 else 1)
 
 
+@pytest.mark.parametrize("prec,n,p", [("c64", 13, 1), ("c64", 13, 64), ("c64", 14, 2),
+                                      ("c64", 14, 64), ("c128", 13, 3), ("c128", 13, 64)])
+def test_whole_state_32_and_64_amplitudes_per_thread(api, prec, n, p):
+    """The whole-state launch at n = 13 and 14 (32 or 64 amplitudes per
+    thread, C(z) formed at each use from the thread's fields and the shared
+    register-bit table): state, <C>, norm and probabilities against the
+    oracle, up to QAOA_MAX_P layers."""
+    Qs, g, b = run_case(api, n, p, S=2, prec=prec, B=2, seed=5)
+    e, P = api.expect(cuda(Qs), cuda(g), cuda(b), prec=prec, probs=True)
+    psi = api.state(cuda(Qs), cuda(g), cuda(b), prec=prec)[0].cpu().numpy()
+    P = P.cpu().numpy()
+    u = 2.0 ** -52 if prec == "c128" else 2.0 ** -23
+    for bi in range(2):
+        for s in range(2):
+            ref = oracle.state(Qs[bi], g[bi, s], b[bi, s])
+            d = np.abs(psi[bi, s].astype(np.complex128) - ref)
+            # |P_gpu - |ref|^2| <= |d| (2 |ref| + |d|) + rounding of |psi|^2
+            bound = d * (2.0 * np.abs(ref) + d) + 4.0 * u * np.abs(ref) ** 2 + 1e-300
+            err = np.abs(P[bi, s].astype(np.float64) - np.abs(ref) ** 2)
+            assert np.all(err <= bound * 1.01 + 1e-18), float(np.max(err - bound))
+
+
 @pytest.mark.parametrize("prec,n", [("c64", 15), ("c128", 14)])
 def test_max_layers_state_and_expect(api, prec, n):
     """QAOA_MAX_P = 64 layers on register tiles (p + 1 = 65 passes on two
