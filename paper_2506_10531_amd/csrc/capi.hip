@@ -509,14 +509,28 @@ int enqueue_sample(const Layout& L, char* base, const double* Q,
                    double* best_c, double* expect, hipStream_t s,
                    PassTimer* tm) {
   void* P = L.at(base, L.iProbs);
-  int rc = run_forward(L, base, Q, gammas, betas, P, nullptr, s, tm);
-  if (rc) return rc;
-  const PassDesc& last = L.plan.pass[L.plan.npass - 1];
-  double* outs[1] = {expect};
-  int q0[1] = {0}, cnt[1] = {1};
-  hipError_t e = launch_reduce_parts((int)L.nstates, (int)ntiles(last), 2,
-                                     (double*)L.at(base, L.iPart), outs, q0, cnt, 1, s);
-  if (e != hipSuccess) return hip_error(e, "reduce");
+  hipError_t e;
+  if (L.plan.npass == 1 && L.n <= small_fwd_nmax(L.prec) && !fwd_reg_off()) {
+    // probabilities and <C> from the whole-state launch; the folded
+    // couplings the shots price their samples with come from prep
+    e = launch_prep(L.B, L.n, Q, (double*)L.at(base, L.iW), (int)L.nstates, L.p, gammas, betas,
+                    (LayerCoef*)L.at(base, L.iC), s);
+    if (e != hipSuccess) return hip_error(e, "prep");
+    TimerScope ts(tm, s, 0.5 * (double)L.state_bytes * L.nstates);
+    e = launch_small_expect(L.prec, L.n, L.p, L.S, (int)L.nstates, Q, gammas, betas,
+                            expect ? expect : (double*)L.at(base, L.iPart), nullptr, P, nullptr,
+                            s);
+    if (e != hipSuccess) return hip_error(e, "whole-state evaluation");
+  } else {
+    int rc = run_forward(L, base, Q, gammas, betas, P, nullptr, s, tm);
+    if (rc) return rc;
+    const PassDesc& last = L.plan.pass[L.plan.npass - 1];
+    double* outs[1] = {expect};
+    int q0[1] = {0}, cnt[1] = {1};
+    e = launch_reduce_parts((int)L.nstates, (int)ntiles(last), 2,
+                            (double*)L.at(base, L.iPart), outs, q0, cnt, 1, s);
+    if (e != hipSuccess) return hip_error(e, "reduce");
+  }
   double* czbuf = cz ? cz : (double*)L.at(base, L.iCz);
   e = launch_sample(L.prec, L.n, (int)L.nstates, P, (double*)L.at(base, L.iBsum),
                     (double*)L.at(base, L.iBcdf), shots, seed, seeds,
