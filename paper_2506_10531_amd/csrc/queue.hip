@@ -20,6 +20,10 @@
 //    groups on separate streams (a HIP graph per recurring group shape).
 //    Requests that finish their evaluations are sampled at the end of the
 //    step and completed.
+//  * A step that ends early samples nothing, so the host does not wait for
+//    its last rounds: the next step's work is ordered after them on the
+//    device (its uploads wait for their events; every stream waits for the
+//    uploads), and the host plans and enqueues it meanwhile.
 //  * The big buffers (checkpoints, adjoint state, probabilities) exist only
 //    within a step; a request's byte charge is what its group needs for it
 //    during a step, so the sum over admitted requests bounds the arena.
@@ -106,6 +110,11 @@ struct qaoa_queue {
   // the step in progress
   std::vector<GroupPlan> gp;
   int nused = 0;
+  int last_round = -1;
+  // A step that ended early for an arrival or a cancellation samples nothing,
+  // so the host does not wait for it: the next step's uploads (stream 0, which
+  // every other stream then waits for) wait on its last round's events instead.
+  int pend_slot = -1, pend_nused = 0;
 
   // Captured evaluation steps: the gather, adjoint pipeline and Adam update
   // of one n-group, replayed while the group's size and its places in the
@@ -171,10 +180,17 @@ int qaoa_queue::eval_group(const GroupPlan& g, hipStream_t s) {
   const GraphKey key{g.g->n, (int)g.g->ev.size(), arena + g.base, dIdx + g.ie};
   auto it = graphs.find(key);
   if (it == graphs.end()) {
-    if (graphs.size() >= 256) {  // evict the least recently used (not in flight:
-      auto lru = graphs.begin();  // every step ends with its streams drained)
+    if (graphs.size() >= 256) {  // evict the least recently used
+      auto lru = graphs.begin();
       for (auto j = graphs.begin(); j != graphs.end(); ++j)
         if (j->second.last < lru->second.last) lru = j;
+      if (lru->second.last + 1 >= step_no) {
+        // used by this step or by the previous one, which may still run
+        for (int i = 0; i < NSTREAMS; ++i) {
+          hipError_t e = hipStreamSynchronize(streams[i]);
+          if (e != hipSuccess) return hip_error(e, "hipStreamSynchronize");
+        }
+      }
       (void)hipGraphExecDestroy(lru->second.exec);
       graphs.erase(lru);
     }
@@ -218,6 +234,17 @@ int qaoa_queue::begin(sched::Step& s) {
   ++step_no;
   const int p = o.p;
   hipStream_t s0 = streams[0];
+  last_round = -1;
+  if (pend_slot >= 0) {
+    // the previous step's last round on every stream precedes this step's
+    // uploads and, through ev_up, all its rounds: slot state, the index
+    // buffer and the arena are reused only after it
+    for (int i = 0; i < pend_nused; ++i) {
+      hipError_t e = hipStreamWaitEvent(s0, ev_round[pend_slot][i], 0);
+      if (e != hipSuccess) return hip_error(e, "hipStreamWaitEvent");
+    }
+    pend_slot = -1;
+  }
   for (size_t i = 0; i < s.fresh.size(); ++i) {
     const Request* r = static_cast<const Request*>(s.fresh[i]);
     double* h = hUp + i * (QN_MAX * QN_MAX + 2 * p + 1);
@@ -319,6 +346,7 @@ int qaoa_queue::round(int k) {
     hipError_t e = hipEventRecord(ev_round[k % 2][i], streams[i]);
     if (e != hipSuccess) return hip_error(e, "hipEventRecord");
   }
+  last_round = k;
   return QAOA_OK;
 }
 
@@ -331,9 +359,15 @@ int qaoa_queue::wait_round(int k) {
 }
 
 // End of a step: sample every group's finished requests at their final
-// parameters and copy the results to the host, then drain the streams.
+// parameters and copy the results to the host, then drain the streams.  A
+// step that samples nothing is left running (see pend_slot).
 int qaoa_queue::end(bool sampled) {
   const int p = o.p;
+  if (!sampled && last_round >= 0) {
+    pend_slot = last_round % 2;
+    pend_nused = nused;
+    return QAOA_OK;
+  }
   for (size_t gi = 0; gi < gp.size() && sampled; ++gi) {
     const GroupPlan& g = gp[gi];
     const int n = g.g->n, ns = (int)g.g->sm.size();
@@ -415,6 +449,7 @@ void qaoa_queue::run() {
       core.fail_active(QAOA_ERR_HIP, now_ns());
       for (int i = 0; i < NSTREAMS; ++i) (void)hipStreamSynchronize(streams[i]);
       (void)hipGetLastError();
+      pend_slot = -1;
     }
   }
 }
