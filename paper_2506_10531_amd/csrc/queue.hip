@@ -105,16 +105,22 @@ struct qaoa_queue {
   // pinned host staging
   double* hUp = nullptr;     // uploads [slots][QN_MAX^2 + 2p]
   int* hIdx = nullptr;       // [2 * slots]
-  char* hRes = nullptr;      // results of one step
+  char* hRes[2] = {};        // results of a sampling step, two buffers in turn
   size_t hRes_bytes = 0;
+  hipEvent_t ev_res[2][NSTREAMS] = {};  // a buffer's copies done, per stream
+  int res_nused[2] = {};
+  int res_next = 0;          // the buffer the next sampling step writes
+  std::vector<sched::Done> deferred;  // sampled requests whose results are in flight
   // the step in progress
   std::vector<GroupPlan> gp;
   int nused = 0;
   int last_round = -1;
-  // A step that ended early for an arrival or a cancellation samples nothing,
-  // so the host does not wait for it: the next step's uploads (stream 0, which
-  // every other stream then waits for) wait on its last round's events instead.
-  int pend_slot = -1, pend_nused = 0;
+  int cur_res = -1;          // its result buffer (sampling steps)
+  // The host waits for no step: the next step's uploads (stream 0, which every
+  // other stream then waits for) wait on the previous step's last work on
+  // each stream: its last round's events, or its result copies' events.
+  const hipEvent_t* pend_ev = nullptr;
+  int pend_nused = 0;
 
   // Captured evaluation steps: the gather, adjoint pipeline and Adam update
   // of one n-group, replayed while the group's size and its places in the
@@ -150,7 +156,9 @@ struct qaoa_queue {
   int round(int k);
   int wait_round(int k);
   int end(bool sampled);
-  void fetch(int gi, int i, sched::Req* r);
+  void defer(const sched::Done& d);
+  int collect(bool wait, std::vector<sched::Done>* out);
+  void fetch(const sched::Done& d);
   int64_t now() const { return now_ns(); }
 };
 
@@ -235,15 +243,15 @@ int qaoa_queue::begin(sched::Step& s) {
   const int p = o.p;
   hipStream_t s0 = streams[0];
   last_round = -1;
-  if (pend_slot >= 0) {
-    // the previous step's last round on every stream precedes this step's
+  if (pend_ev) {
+    // the previous step's last work on every stream precedes this step's
     // uploads and, through ev_up, all its rounds: slot state, the index
     // buffer and the arena are reused only after it
     for (int i = 0; i < pend_nused; ++i) {
-      hipError_t e = hipStreamWaitEvent(s0, ev_round[pend_slot][i], 0);
+      hipError_t e = hipStreamWaitEvent(s0, pend_ev[i], 0);
       if (e != hipSuccess) return hip_error(e, "hipStreamWaitEvent");
     }
-    pend_slot = -1;
+    pend_ev = nullptr;
   }
   for (size_t i = 0; i < s.fresh.size(); ++i) {
     const Request* r = static_cast<const Request*>(s.fresh[i]);
@@ -358,17 +366,23 @@ int qaoa_queue::wait_round(int k) {
   return QAOA_OK;
 }
 
-// End of a step: sample every group's finished requests at their final
-// parameters and copy the results to the host, then drain the streams.  A
-// step that samples nothing is left running (see pend_slot).
+// End of a step.  A step that samples enqueues, per group, the sampling of
+// its finished requests at their final parameters and the copy of their
+// results into a host buffer that holds no uncollected results, and records
+// when the copies are done; no step is waited for here.
 int qaoa_queue::end(bool sampled) {
   const int p = o.p;
-  if (!sampled && last_round >= 0) {
-    pend_slot = last_round % 2;
-    pend_nused = nused;
+  if (!sampled) {
+    if (last_round >= 0) {
+      pend_ev = ev_round[last_round % 2];
+      pend_nused = nused;
+    }
     return QAOA_OK;
   }
-  for (size_t gi = 0; gi < gp.size() && sampled; ++gi) {
+  const int rb = res_next;
+  res_next ^= 1;
+  cur_res = rb;
+  for (size_t gi = 0; gi < gp.size(); ++gi) {
     const GroupPlan& g = gp[gi];
     const int n = g.g->n, ns = (int)g.g->sm.size();
     if (!ns) continue;
@@ -386,7 +400,7 @@ int qaoa_queue::end(bool sampled) {
     int rc = enqueue_sample(g.ls, A(g.iSamp), Q, gg, bb, o.shots, 0, sd, z, nullptr, bz, bc, es,
                             s, nullptr);
     if (rc) return rc;
-    char* hr = hRes + g.res;
+    char* hr = hRes[rb] + g.res;
     e = hipMemcpyAsync(hr, z, (size_t)ns * o.shots * 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
       e = hipMemcpyAsync(hr + (size_t)ns * o.shots * 8, gg, (size_t)ns * p * 8,
@@ -405,16 +419,46 @@ int qaoa_queue::end(bool sampled) {
                          hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return hip_error(e, "result copy");
   }
-  for (int i = 0; i < NSTREAMS; ++i) {
-    hipError_t e = hipStreamSynchronize(streams[i]);
-    if (e != hipSuccess) return hip_error(e, "hipStreamSynchronize");
+  for (int i = 0; i < nused; ++i) {
+    hipError_t e = hipEventRecord(ev_res[rb][i], streams[i]);
+    if (e != hipSuccess) return hip_error(e, "hipEventRecord");
   }
+  res_nused[rb] = nused;
+  pend_ev = ev_res[rb];
+  pend_nused = nused;
   return QAOA_OK;
 }
 
-void qaoa_queue::fetch(int gi, int i, sched::Req* r) {
-  const int p = o.p, ns = (int)gp[gi].g->sm.size();
-  const char* hr = hRes + gp[gi].res;
+void qaoa_queue::defer(const sched::Done& d) {
+  sched::Done x = d;
+  x.buf = cur_res;
+  x.off = gp[d.gi].res;
+  x.ns = (int)gp[d.gi].g->sm.size();
+  deferred.push_back(x);
+}
+
+// The deferred requests, once every copy into their buffer is done (they
+// all share one buffer: a sampling step collects the previous one's first).
+int qaoa_queue::collect(bool wait, std::vector<sched::Done>* out) {
+  if (deferred.empty()) return QAOA_OK;
+  const int rb = deferred.front().buf;
+  for (int i = 0; i < res_nused[rb]; ++i) {
+    hipError_t e = wait ? hipEventSynchronize(ev_res[rb][i]) : hipEventQuery(ev_res[rb][i]);
+    if (e == hipErrorNotReady) {
+      (void)hipGetLastError();  // not an error: leave no trace for later launch checks
+      return QAOA_OK;
+    }
+    if (e != hipSuccess) return hip_error(e, "result event");
+  }
+  out->swap(deferred);
+  deferred.clear();
+  return QAOA_OK;
+}
+
+void qaoa_queue::fetch(const sched::Done& d) {
+  const int p = o.p, ns = d.ns, i = d.i;
+  sched::Req* r = d.r;
+  const char* hr = hRes[d.buf] + d.off;
   const uint64_t* z = (const uint64_t*)hr;
   const double* gg = (const double*)(hr + (size_t)ns * o.shots * 8);
   const double* bb = (const double*)(hr + (size_t)ns * (o.shots + p) * 8);
@@ -434,22 +478,27 @@ void qaoa_queue::fetch(int gi, int i, sched::Req* r) {
 void qaoa_queue::run() {
   (void)hipSetDevice(device);
   for (;;) {
+    int running = 0;
     {
       std::unique_lock<std::mutex> lk(core.mu);
       for (;;) {
-        const int resident = core.admit(now_ns());
+        core.admit(now_ns());
         if (core.stop) return;
-        if (resident) break;
+        running = core.count(1);
+        if (running || core.count(3)) break;
         core.cv_sched.wait(lk);
       }
     }
-    if (sched::run_step(core, *this) != QAOA_OK) {
-      // fail every admitted request of this step; keep serving the rest
+    // with nothing to run, wait for the results still on their way
+    const int rc = running ? sched::run_step(core, *this) : sched::finish_sampled(core, *this, true);
+    if (rc != QAOA_OK) {
+      // fail every resident request; keep serving the rest
       std::lock_guard<std::mutex> lk(core.mu);
       core.fail_active(QAOA_ERR_HIP, now_ns());
       for (int i = 0; i < NSTREAMS; ++i) (void)hipStreamSynchronize(streams[i]);
       (void)hipGetLastError();
-      pend_slot = -1;
+      pend_ev = nullptr;
+      deferred.clear();
     }
   }
 }
@@ -513,7 +562,11 @@ int qaoa_queue_create(qaoa_ctx* ctx, const qaoa_queue_opts* opts, qaoa_queue** o
     e = hipHostMalloc((void**)&q->hUp, sizeof(double) * S * (QN_MAX * QN_MAX + 2 * p + 1), 0);
   if (e == hipSuccess) e = hipHostMalloc((void**)&q->hIdx, sizeof(int) * 2 * S, 0);
   q->hRes_bytes = (size_t)S * (o.shots + 2 * p + 3) * 8;
-  if (e == hipSuccess) e = hipHostMalloc((void**)&q->hRes, q->hRes_bytes, 0);
+  for (int r = 0; r < 2; ++r) {
+    if (e == hipSuccess) e = hipHostMalloc((void**)&q->hRes[r], q->hRes_bytes, 0);
+    for (int i = 0; i < NSTREAMS && e == hipSuccess; ++i)
+      e = hipEventCreateWithFlags(&q->ev_res[r][i], hipEventDisableTiming);
+  }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     qaoa_queue* qq = q.release();
@@ -546,10 +599,13 @@ int qaoa_queue_destroy(qaoa_queue* q) {
   for (int r = 0; r < 2; ++r)
     for (int i = 0; i < NSTREAMS; ++i)
       if (q->ev_round[r][i]) (void)hipEventDestroy(q->ev_round[r][i]);
+  for (int r = 0; r < 2; ++r)
+    for (int i = 0; i < NSTREAMS; ++i)
+      if (q->ev_res[r][i]) (void)hipEventDestroy(q->ev_res[r][i]);
   void* dev[] = {q->arena, q->dQ, q->dG, q->dB, q->dM, q->dV, q->dT, q->dSeed, q->dIdx};
   for (void* ptr : dev)
     if (ptr) (void)hipFree(ptr);
-  void* host[] = {q->hUp, q->hIdx, q->hRes};
+  void* host[] = {q->hUp, q->hIdx, q->hRes[0], q->hRes[1]};
   for (void* ptr : host)
     if (ptr) (void)hipHostFree(ptr);
   delete q;

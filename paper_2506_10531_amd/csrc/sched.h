@@ -16,8 +16,14 @@
 //    k >= 2 the step waits for round k - 2 and ends there if a waiting
 //    request could now be admitted or a running one was cancelled, so an
 //    arrival waits at most about two evaluations while the device stays busy;
+//  * results: a step that samples hands its finished requests' results to
+//    the backend, which copies them back while later steps run; those
+//    requests keep their slots ("sampled") until the results are collected,
+//    at the start of a later step, before the next sampling step, or when
+//    nothing else runs;
 //  * cancellation: a pending request completes as cancelled at once, a
-//    running one at the next step boundary;
+//    running one at the next step boundary, a sampled one when its results
+//    arrive;
 //  * bookkeeping: evaluation counts, completion, slot and byte release,
 //    timestamps and counters.
 //
@@ -28,9 +34,16 @@
 //   int  round(int k)          enqueue evaluation round k of every group;
 //   int  wait_round(int k)     block until round k has finished;
 //   int  end(bool sampled)     enqueue sampling of the groups' finished
-//                              requests if `sampled`, then wait for all work;
-//   void fetch(int g, int i, Req* r)  results of request i of group g's
-//                              sampled list into r (lock held);
+//                              requests and the copy of their results if
+//                              `sampled` (into a result buffer that holds no
+//                              uncollected results);
+//   void defer(const Done&)    remember that request i of group g's sampled
+//                              list has its results in that buffer (lock held);
+//   int  collect(bool wait, std::vector<Done>*)  the deferred requests whose
+//                              results have arrived (all of them, waiting,
+//                              if `wait`);
+//   void fetch(const Done&)    copy a collected request's results into it
+//                              (lock held);
 //   int64_t now()              the clock timestamps are taken from.
 #ifndef DQ_SCHED_H
 #define DQ_SCHED_H
@@ -57,7 +70,7 @@ struct Req {
   uint64_t id = 0;
   int n = 0;
   size_t bytes = 0;  // device bytes charged while admitted
-  int state = 0;     // 0 pending, 1 admitted, 2 done
+  int state = 0;     // 0 pending, 1 admitted, 2 done, 3 sampled (results on their way)
   bool cancel = false;
   bool uploaded = false;
   int slot = -1;
@@ -72,6 +85,16 @@ struct Group {
   int n = 0;
   std::vector<Req*> ev;  // evaluated in every round of the step
   std::vector<Req*> sm;  // sampled and completed if the step runs all K rounds
+};
+
+// A sampled request whose results the backend copies back: request i of
+// group gi's sampled list in step-local numbering; the backend records where
+// the results go (buffer, offset, size of the group's list).
+struct Done {
+  Req* r = nullptr;
+  int gi = 0, i = 0;
+  int buf = 0, ns = 0;
+  size_t off = 0;
 };
 
 struct Step {
@@ -133,7 +156,7 @@ struct Core {
     r->res.status = status;
     r->res.n = r->n;
     r->res.t_done_ns = now;
-    if (r->state == 1) {
+    if (r->state == 1 || r->state == 3) {
       in_use -= r->bytes;
       slots[r->slot] = nullptr;
       free_slots.push_back(r->slot);
@@ -145,11 +168,12 @@ struct Core {
     cv_done.notify_all();
   }
 
-  // Between steps: cancelled admitted requests complete, then FIFO admission
-  // against free slots and the budget.  Returns the requests resident after.
+  // Between steps: cancelled running requests complete, then FIFO admission
+  // against free slots and the budget.  Returns the requests resident after
+  // (running or sampled).
   int admit(int64_t now) {
     for (Req* r : slots)
-      if (r && r->cancel) complete(r, QAOA_ERR_CANCELLED, now);
+      if (r && r->cancel && r->state == 1) complete(r, QAOA_ERR_CANCELLED, now);
     while (!pending.empty() && !free_slots.empty()) {
       Req* r = reqs.at(pending.front()).get();
       if (in_use + r->bytes > budget) break;
@@ -169,10 +193,17 @@ struct Core {
     return resident;
   }
 
-  // The next step over the admitted requests; false if there are none.
+  // Resident requests in `state` (1 running, 3 sampled).
+  int count(int state) const {
+    int c = 0;
+    for (Req* r : slots) c += r && r->state == state;
+    return c;
+  }
+
+  // The next step over the running requests; false if there are none.
   bool plan(Step* s) {
     for (Req* r : slots)
-      if (r && !r->cancel) {
+      if (r && !r->cancel && r->state == 1) {
         s->act.push_back(r);
         if (!r->uploaded) s->fresh.push_back(r);
       }
@@ -207,7 +238,8 @@ struct Core {
     return in_use + reqs.at(pending.front())->bytes <= budget;
   }
 
-  // After a failed step: every admitted request completes with `status`.
+  // After a failed step: every resident request (running or sampled)
+  // completes with `status`.
   void fail_active(int status, int64_t now) {
     for (Req* r : slots)
       if (r) complete(r, status, now);
@@ -258,16 +290,35 @@ struct Core {
   }
 };
 
-// One step over the admitted requests (see the header comment).  Called
+// Collects the sampled requests whose results have arrived (all of them,
+// waiting, if `wait`) and completes them.  Called without the lock.
+template <class Backend>
+int finish_sampled(Core& c, Backend& b, bool wait) {
+  std::vector<Done> done;
+  int rc = b.collect(wait, &done);
+  if (rc) return rc;
+  if (done.empty()) return QAOA_OK;
+  std::lock_guard<std::mutex> lk(c.mu);
+  for (const Done& d : done) {
+    if (d.r->state != 3) continue;  // completed otherwise meanwhile
+    b.fetch(d);
+    c.complete(d.r, d.r->cancel ? QAOA_ERR_CANCELLED : QAOA_OK, b.now());
+  }
+  return QAOA_OK;
+}
+
+// One step over the running requests (see the header comment).  Called
 // without the lock; takes it for planning and bookkeeping only.
 template <class Backend>
 int run_step(Core& c, Backend& b) {
+  int rc = finish_sampled(c, b, false);
+  if (rc) return rc;
   Step s;
   {
     std::lock_guard<std::mutex> lk(c.mu);
     if (!c.plan(&s)) return QAOA_OK;
   }
-  int rc = b.begin(s);
+  rc = b.begin(s);
   if (rc) return rc;
   for (Req* r : s.fresh) r->uploaded = true;
   int Kdone = s.K;
@@ -285,7 +336,14 @@ int run_step(Core& c, Backend& b) {
     if (rc) return rc;
   }
   // requests reach their last evaluation only when the step ran all K rounds
-  const bool sampled = Kdone == s.K;
+  // (K is the fewest evaluations any request has left)
+  bool sampled = false;
+  if (Kdone == s.K)
+    for (auto& kv : s.groups) sampled = sampled || !kv.second.sm.empty();
+  if (sampled) {
+    rc = finish_sampled(c, b, true);  // frees a result buffer
+    if (rc) return rc;
+  }
   rc = b.end(sampled);
   if (rc) return rc;
   std::lock_guard<std::mutex> lk(c.mu);
@@ -295,8 +353,8 @@ int run_step(Core& c, Backend& b) {
     for (Req* r : g.ev) r->evals_done += Kdone;
     if (sampled)
       for (size_t i = 0; i < g.sm.size(); ++i) {
-        b.fetch(gi, (int)i, g.sm[i]);
-        c.complete(g.sm[i], QAOA_OK, b.now());
+        g.sm[i]->state = 3;
+        b.defer(Done{g.sm[i], gi, (int)i});
       }
     ++gi;
   }

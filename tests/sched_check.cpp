@@ -111,6 +111,8 @@ struct Fake {
   size_t next_action = 0;
   int fail_round = -1;  // fail round k of the next step that reaches it
   long rounds = 0, steps = 0;
+  std::vector<Done> deferred;  // sampled, results not collected yet
+  int64_t res_at = 0;          // when they arrive
 
   Fake(Core& core, int nslots, int ev) : c(core), evals(ev), x(nslots), count(nslots),
                                          owner(nslots) {}
@@ -132,7 +134,7 @@ struct Fake {
         if (r) {
           bytes += r->bytes;
           ++resident;
-          CHECK(r->state == 1 && c.slots[r->slot] == r, "slot table");
+          CHECK((r->state == 1 || r->state == 3) && c.slots[r->slot] == r, "slot table");
         }
       CHECK(bytes == c.in_use && c.in_use <= c.budget, "bytes %zu in_use %zu budget %zu", bytes,
             c.in_use, c.budget);
@@ -202,25 +204,38 @@ struct Fake {
     return QAOA_OK;
   }
 
-  // A step that samples nothing is not waited for (the device queue orders
-  // the next step's work after it); a sampling step drains.
+  // No step is waited for (the device queue orders the next step's work
+  // after it); a sampling step's results arrive when its sampling is done.
   int end(bool sampled) {
-    if (!sampled) {
-      fire();
-      return QAOA_OK;
+    if (sampled) {
+      CHECK(deferred.empty(), "a sampling step with results still uncollected");
+      int64_t cost = 0;
+      for (auto& kv : step->groups) cost += 3000 + (int64_t)kv.second.sm.size() * 200;
+      sample_cost = std::max(sample_cost, cost);
+      dev_free = std::max(dev_free, t) + cost;
+      res_at = dev_free;
     }
-    int64_t cost = 0;
-    for (auto& kv : step->groups) cost += 3000 + (int64_t)kv.second.sm.size() * 200;
-    sample_cost = std::max(sample_cost, cost);
-    dev_free = std::max(dev_free, t) + cost;
-    t = dev_free;
     fire();
     return QAOA_OK;
   }
 
-  void fetch(int gi, int i, Req* r) {
-    (void)gi;
-    (void)i;
+  void defer(const Done& d) {
+    CHECK(d.r->state == 3, "deferred request not sampled");
+    deferred.push_back(d);
+  }
+
+  int collect(bool wait, std::vector<Done>* out) {
+    if (deferred.empty()) return QAOA_OK;
+    if (wait) t = std::max(t, res_at);
+    if (t < res_at) return QAOA_OK;
+    out->swap(deferred);
+    deferred.clear();
+    fire();
+    return QAOA_OK;
+  }
+
+  void fetch(const Done& d) {
+    Req* r = d.r;
     const TReq* q = static_cast<const TReq*>(r);
     const int sl = r->slot;
     CHECK(owner[sl] == r->id, "fetch from a slot the request does not hold");
@@ -297,15 +312,19 @@ Run serve(const std::vector<Spec>& trace, const Opts& o) {
       break;
     }
     f.fire();
-    int resident;
+    int running, sampled;
     {
       std::lock_guard<std::mutex> lk(c.mu);
-      resident = c.admit(f.t);
+      c.admit(f.t);
+      running = c.count(1);
+      sampled = c.count(3);
     }
-    if (resident) {
-      if (run_step(c, f) != QAOA_OK) {
+    if (running || sampled) {
+      const int rc = running ? run_step(c, f) : finish_sampled(c, f, true);
+      if (rc != QAOA_OK) {
         std::lock_guard<std::mutex> lk(c.mu);
         c.fail_active(QAOA_ERR_HIP, f.t);
+        f.deferred.clear();
       }
       continue;
     }
@@ -513,6 +532,47 @@ void test_failed_step() {
   CHECK(failed >= 1 && failed <= o.slots && ok == 30 - failed, "failed %d ok %d", failed, ok);
 }
 
+// A request whose results are on their way keeps its slot, is not planned
+// again, reads as pending, and completes as cancelled if cancelled then.
+void test_results_in_flight() {
+  Core c;
+  c.init(2, 8, 1 << 20, 2);
+  Fake f(c, 2, 2);
+  auto mk = [](uint64_t seed) {
+    std::unique_ptr<TReq> r(new TReq());
+    r->n = 6;
+    r->bytes = 1000;
+    r->a = 0.7;
+    r->b = 0.2;
+    r->x0 = 0.3;
+    r->seed = seed;
+    return r;
+  };
+  uint64_t ta = 0, tb = 0;
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    CHECK(c.submit(mk(1), 0, &ta) == QAOA_OK && c.submit(mk(2), 0, &tb) == QAOA_OK, "submit");
+    CHECK(c.admit(0) == 2, "both admitted");
+  }
+  CHECK(run_step(c, f) == QAOA_OK, "step");  // two rounds, then both sampled
+  {
+    std::lock_guard<std::mutex> lk(c.mu);
+    CHECK(c.count(3) == 2 && c.count(1) == 0 && c.in_use == 2000, "sampled, slots held");
+    CHECK(c.take(ta, nullptr, nullptr) == QAOA_PENDING, "results not collected yet");
+    Step s;
+    CHECK(!c.plan(&s), "sampled requests are not planned");
+    CHECK(c.cancel(ta, f.t) == QAOA_OK, "cancel while results are on their way");
+    CHECK(c.admit(f.t) == 2 && c.count(3) == 2, "a sampled request leaves only when collected");
+  }
+  CHECK(finish_sampled(c, f, true) == QAOA_OK, "collect");
+  std::lock_guard<std::mutex> lk(c.mu);
+  qaoa_solve_result ra{}, rb{};
+  CHECK(c.take(ta, &ra, nullptr) == QAOA_OK && ra.status == QAOA_ERR_CANCELLED, "cancelled");
+  CHECK(c.take(tb, &rb, nullptr) == QAOA_OK && rb.status == QAOA_OK && rb.beta[0] == 2.0,
+        "completed after two evaluations");
+  CHECK(c.in_use == 0 && c.count(3) == 0, "slots released");
+}
+
 // evals = 0: one step samples every request at its initial parameters.
 void test_no_evaluations() {
   const auto trace = make_trace(12, 3, 3, 8, 500);
@@ -532,6 +592,7 @@ void test_no_evaluations() {
 int main() {
   test_backpressure_and_budget();
   test_no_evaluations();
+  test_results_in_flight();
   test_cancel_running();
   test_failed_step();
   test_arrival_latency();
