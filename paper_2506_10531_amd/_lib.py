@@ -119,7 +119,7 @@ def load(path: str | None = None):
     if not os.path.exists(so):
         raise RuntimeError(
             f"{so} is missing: build the HIP library first "
-            "(python -c 'import __graft_entry__ as g; g.build()')")
+            "(python -m paper_2506_10531_amd.build)")
     L = ctypes.CDLL(so)
     vp, i, u64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_size_t
     dp = ctypes.c_void_p
