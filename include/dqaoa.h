@@ -259,7 +259,10 @@ typedef struct {
 
 int qaoa_queue_create(qaoa_ctx* ctx, const qaoa_queue_opts* opts,
                       qaoa_queue** out);
-/* Cancels pending and running requests, joins the scheduler, frees memory. */
+/* Stops and joins the scheduler, waits for the device work in flight and
+ * frees the queue.  Requests not completed by then are dropped with it (their
+ * tickets become invalid); no other call on the queue may be in progress or
+ * follow (in particular no qaoa_wait on another thread). */
 int qaoa_queue_destroy(qaoa_queue* q);
 /* Thread-safe.  Copies Q and the initial parameters (host memory) before
  * returning.  Errors: QAOA_ERR_INVALID_ARG, QAOA_ERR_QUEUE_FULL (pending at
