@@ -203,3 +203,30 @@ def test_sampling_matches_oracle_draws(api, prec, n, p):
         eo = oracle.expect(Qs[bi], g[bi], b[bi])[0][0]
         etol = 1e-10 * max(1.0, abs(eo)) if prec == "c128" else 1e-5 * np.max(np.abs(C))
         assert abs(ex[bi] - eo) <= etol
+
+
+@pytest.mark.parametrize("prec,n", [("c64", 10), ("c128", 13), ("c64", 16)])
+def test_sampling_nullable_outputs(api, prec, n):
+    """qaoa_sample with cz and expect NULL (the whole-state launch at n <= 14 /
+    13 then writes <C> to scratch) draws exactly what the call with every
+    output does."""
+    import ctypes
+
+    from paper_2506_10531_amd import _lib
+    B, shots, seed, p = 3, 512, 777, 2
+    Qs = workloads.qubos(B, n, 3700 + n)
+    g, b = workloads.params(1, p, 3800 + n, lead=(B,))
+    Qd, gd, bd = cuda(Qs), cuda(g[:, 0]), cuda(b[:, 0])
+    full = api.sample(Qd, gd, bd, shots, seed, prec=prec)
+    z = torch.empty((B, shots), dtype=torch.int64, device="cuda:0")
+    bz = torch.empty((B,), dtype=torch.int64, device="cuda:0")
+    bc = torch.empty((B,), dtype=torch.float64, device="cuda:0")
+    ctx = api.default_context(0)
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())
+    rc = _lib.load().qaoa_sample(ctx.h, api.PREC[prec], B, n, p, vp(Qd), vp(gd), vp(bd), shots,
+                                 seed, vp(z), None, vp(bz), vp(bc), None,
+                                 ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == 0, _lib.load().qaoa_last_error()
+    torch.cuda.synchronize()
+    assert torch.equal(z, full["z"]) and torch.equal(bz, full["best_z"])
+    assert torch.equal(bc, full["best_c"])
