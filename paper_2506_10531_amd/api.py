@@ -148,6 +148,54 @@ def expect(Q, gammas, betas, prec="c64", probs=False, norm=False, ctx=None):
     return out[0] if len(out) == 1 else tuple(out)
 
 
+class Evaluator:
+    """Repeated <C> evaluations of fixed problems, for optimiser loops.
+
+    Q ([B,n,n] or [n,n]), the number of parameter sets S, the depth p, the
+    precision and the output buffers are bound once; each call passes new
+    gammas and betas (float64 [B,S,p], contiguous, on Q's GPU) to one
+    qaoa_expect on the stream that was current when the evaluator was made,
+    and returns the bound <C> tensor [B,S] (overwritten by the next call;
+    `norm` and `probs` likewise when requested).  It saves the per-call
+    argument handling and output allocation of expect()."""
+
+    def __init__(self, Q, S: int, p: int, prec="c64", probs=False, norm=False, ctx=None):
+        Q = _dev(Q, "Q")
+        if Q.dim() == 2:
+            Q = Q.unsqueeze(0)
+        B, n, n2 = Q.shape
+        if n != n2:
+            raise ValueError("Q must be square")
+        pc = _prec(prec)
+        self.Q = Q
+        self.shape = torch.Size((B, int(S), int(p)))
+        self.device = Q.device
+        self.ctx = ctx or default_context(Q.device.index)
+        self.expect = torch.empty((B, S), dtype=torch.float64, device=Q.device)
+        self.norm = torch.empty((B, S), dtype=torch.float64, device=Q.device) if norm else None
+        self.probs = None
+        if probs:
+            dt = torch.float64 if pc == _lib.QAOA_C128 else torch.float32
+            self.probs = torch.empty((B, S, 1 << n), dtype=dt, device=Q.device)
+        self._fn = _lib.load().qaoa_expect
+        self._head = (self.ctx.h, pc, B, n, int(p), int(S), Q.data_ptr())
+        self._tail = (self.expect.data_ptr(),
+                      self.norm.data_ptr() if norm else None,
+                      self.probs.data_ptr() if probs else None,
+                      torch.cuda.current_stream(Q.device).cuda_stream)
+
+    def __call__(self, gammas: torch.Tensor, betas: torch.Tensor) -> torch.Tensor:
+        for t in (gammas, betas):
+            if (t.shape != self.shape or t.dtype != torch.float64 or t.device != self.device
+                    or not t.is_contiguous()):
+                raise ValueError(f"gammas and betas must be contiguous float64 {tuple(self.shape)} "
+                                 f"on {self.device}")
+        rc = self._fn(*self._head, gammas.data_ptr(), betas.data_ptr(), *self._tail)
+        if rc:
+            _lib.check(rc)
+        return self.expect
+
+
 def expect_noalloc(Q, gammas, betas, out, norm=None, probs=None, prec="c64", ctx=None):
     """qaoa_expect_noalloc: <C> into the caller's ``out`` [B, S] (and norms
     [B, S], |psi|^2 [B, S, 2^n] if given) with no device allocation by the

@@ -711,10 +711,12 @@ int noalloc_setup(int device) {
 }
 
 struct DeviceGuard {
-  int prev = -1;
+  int prev = -1;  // the device to restore, -1 if none
   bool ok = true;
   explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur == dev) return;  // already current
+    prev = cur;
     ok = hipSetDevice(dev) == hipSuccess;
   }
   ~DeviceGuard() {

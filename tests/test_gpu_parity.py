@@ -164,3 +164,23 @@ def test_deterministic_repeat(api):
     a1 = api.expect(cuda(Q), cuda(g), cuda(b), prec="c64").cpu().numpy()
     a2 = api.expect(cuda(Q), cuda(g), cuda(b), prec="c64").cpu().numpy()
     assert np.array_equal(a1, a2)
+
+
+@pytest.mark.parametrize("prec,n", [("c128", 10), ("c64", 13), ("c64", 16)])
+def test_evaluator_matches_expect(api, prec, n):
+    """api.Evaluator (problem and outputs bound once, one qaoa_expect per call)
+    returns bitwise what api.expect returns for the same parameters, call
+    after call, and refuses parameters of another shape."""
+    B, S, p = 2, 5, 3
+    Qs = workloads.qubos(B, n, 6100 + n)
+    Qd = cuda(Qs)
+    ev = api.Evaluator(Qd, S, p, prec=prec, probs=True, norm=True)
+    for trial in range(3):
+        g, b = workloads.params(S, p, 6200 + 10 * n + trial, lead=(B,))
+        gd, bd = cuda(g), cuda(b)
+        e = ev(gd, bd).clone()
+        e2, nr2, P2 = api.expect(Qd, gd, bd, prec=prec, probs=True, norm=True)
+        torch.cuda.synchronize()
+        assert torch.equal(e, e2) and torch.equal(ev.norm, nr2) and torch.equal(ev.probs, P2)
+    with pytest.raises(ValueError):
+        ev(gd[:, :2].contiguous(), bd[:, :2].contiguous())
