@@ -169,12 +169,14 @@ def test_autograd_function(api):
                                       ("c128", 19, 2), ("c128", 22, 3), ("c128", 24, 1),
                                       ("c64", 10, 3), ("c64", 14, 2), ("c64", 18, 2),
                                       ("c64", 19, 3), ("c64", 20, 2), ("c64", 21, 2),
-                                      ("c64", 22, 3), ("c64", 24, 2)])
+                                      ("c64", 22, 3), ("c64", 24, 2), ("c64", 25, 2),
+                                      ("c128", 25, 1)])
 def test_sampling_matches_oracle_draws(api, prec, n, p):
     """Every register-tile probability store: complex64 n = 19..24 keep 7 down
     to 4 contiguous low qubits in the last pass's set (first mixed bit 4..7),
-    complex128 n = 19..24 the 13-qubit plans."""
-    B, shots, seed = (3 if n <= 21 else 2), 2048, 12345
+    complex128 n = 19..24 the 13-qubit plans, and n = 25 the three-set plans
+    (their last pass on the last set after a lead-only pass)."""
+    B, shots, seed = (3 if n <= 21 else 2 if n <= 24 else 1), 2048, 12345
     Qs = workloads.qubos(B, n, 3500 + n)
     g, b = workloads.params(1, p, 3600 + n, lead=(B,))
     r = api.sample(cuda(Qs), cuda(g[:, 0]), cuda(b[:, 0]), shots, seed, prec=prec)
