@@ -184,3 +184,32 @@ def test_evaluator_matches_expect(api, prec, n):
         assert torch.equal(e, e2) and torch.equal(ev.norm, nr2) and torch.equal(ev.probs, P2)
     with pytest.raises(ValueError):
         ev(gd[:, :2].contiguous(), bd[:, :2].contiguous())
+
+
+@pytest.mark.parametrize("prec,n,B,S,p", [("c128", 3, 3, 21845, 2), ("c64", 3, 3, 21845, 2),
+                                          ("c64", 15, 1, 65535, 1)])
+def test_max_states_per_call(api, prec, n, B, S, p):
+    """B * S = 65535, the most states one call takes: the whole-state launch
+    (one work-group per state, n = 3: every set against the oracle) and the
+    register-tile passes (n = 15: 2 tiles per state, 131070 work-groups, 17 GB
+    of state; 16 sets spread over the range against the oracle).  One state
+    more is rejected before any work."""
+    from paper_2506_10531_amd import _lib
+    print(f"max states {prec} n={n} B={B} S={S} p={p}", flush=True)
+    Qs = workloads.qubos(B, n, 7100 + n)
+    g, b = workloads.params(S, p, 7200 + n, lead=(B,))
+    ctx = api.Context(0)  # its 18 GB of scratch go with it
+    e = api.expect(cuda(Qs), cuda(g), cuda(b), prec=prec, ctx=ctx).cpu().numpy()
+    ctx.close()
+    for bi in range(B):
+        sets = np.arange(S) if n <= 8 else np.linspace(0, S - 1, 16).astype(int)
+        eo = oracle.expect(Qs[bi], g[bi][sets], b[bi][sets])[0]
+        tol = TOL_E[prec](0.0, cmax(Qs[bi]))
+        if prec == "c128":
+            tol = 1e-10 * np.maximum(np.abs(eo), 1.0)
+        assert np.all(np.abs(e[bi][sets] - eo) <= tol), bi
+    torch.cuda.synchronize()
+    g1, b1 = workloads.params(65536, 1, 7300)
+    with pytest.raises(_lib.QaoaError) as ei:
+        api.expect(cuda(Qs[0]), cuda(g1), cuda(b1), prec=prec)
+    assert ei.value.code == _lib.ERR_INVALID_ARG
