@@ -213,3 +213,21 @@ def test_max_states_per_call(api, prec, n, B, S, p):
     with pytest.raises(_lib.QaoaError) as ei:
         api.expect(cuda(Qs[0]), cuda(g1), cuda(b1), prec=prec)
     assert ei.value.code == _lib.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("prec,n", [("c128", 5), ("c64", 13), ("c64", 18), ("c128", 16),
+                                    ("c64", 25)])
+def test_zero_q_is_exact(api, prec, n):
+    """Q = 0: C(z) = 0 for every z, so <C> is exactly 0 and, |+> being an
+    eigenstate of every mixer, the state stays uniform up to a global phase:
+    every probability 2^-n, the norm 1."""
+    B, S, p = 1, 2, 3
+    Q = np.zeros((B, n, n))
+    g, b = workloads.params(S, p, 7400 + n, lead=(B,))
+    e, nr = api.expect(cuda(Q), cuda(g), cuda(b), prec=prec, norm=True)
+    assert torch.all(e == 0.0), e
+    tol = 1e-14 if prec == "c128" else 2e-6
+    assert torch.all(torch.abs(nr - 1.0) <= tol), nr
+    psi = api.state(cuda(Q), cuda(g), cuda(b), prec=prec)[0].cpu().numpy()
+    P = np.abs(psi.astype(np.complex128)) ** 2
+    assert np.max(np.abs(P * 2.0 ** n - 1.0)) <= (1e-12 if prec == "c128" else 1e-5)
