@@ -33,8 +33,8 @@
 // gamma = 0 uniformity and the mean of C, the diagonal-Q product formula,
 // conjugation and beta + pi symmetries, exhaustive argmin against itertools,
 // the adjoint gradient against central finite differences, and sampling
-// frequencies against a chi-square test.  The Adam trajectory is "parity
-// unpinned" beyond its first step (see the test of adam_solve).
+// frequencies against a chi-square test; the solve loop's Adam trajectory
+// against torch.optim.Adam, an independent implementation of the method.
 
 #include <cmath>
 #include <complex>

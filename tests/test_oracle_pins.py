@@ -243,6 +243,33 @@ def test_adam_first_step_closed_form_and_descent():
     r1 = oracle.adam_solve(Q, g0[0], b0[0], evals=1, lr=lr, shots=16, seed=1)
     assert r1["gamma"] == pytest.approx(g0[0] - lr * dg[0] / (np.abs(dg[0]) + 1e-8), abs=1e-14)
     assert r1["beta"] == pytest.approx(b0[0] - lr * db[0] / (np.abs(db[0]) + 1e-8), abs=1e-14)
-    # 100 steps decrease <C> (parity of the trajectory itself is unpinned)
+    # 100 steps decrease <C>
     r100 = oracle.adam_solve(Q, g0[0], b0[0], evals=100, lr=lr, shots=64, seed=1)
     assert r100["expect"] < e0
+
+
+@pytest.mark.parametrize("lr,b1,b2,eps", [(0.05, 0.9, 0.999, 1e-8), (0.1, 0.8, 0.99, 1e-6)])
+def test_adam_trajectory_matches_torch_adam(lr, b1, b2, eps):
+    """The solve loop's whole trajectory against an independent implementation
+    of Adam (Kingma & Ba 2015), torch.optim.Adam on the CPU in FP64, fed the
+    oracle's adjoint gradient (itself pinned against finite differences) at
+    each iterate: the iterates after 1, 2, 3, 10 and 40 steps agree to 1e-12."""
+    torch = pytest.importorskip("torch")
+    n, p = 8, 2
+    Q = workloads.qubos(1, n, 1700)[0]
+    g0, b0 = workloads.params(1, p, 1701)
+    th = torch.tensor(np.concatenate([g0[0], b0[0]]), dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([th], lr=lr, betas=(b1, b2), eps=eps)
+    traj = []
+    for _ in range(40):
+        x = th.detach().numpy()
+        _, dg, db = oracle.grad(Q, x[None, :p], x[None, p:])
+        opt.zero_grad()
+        th.grad = torch.tensor(np.concatenate([dg[0], db[0]]), dtype=torch.float64)
+        opt.step()
+        traj.append(th.detach().numpy().copy())
+    for k in (1, 2, 3, 10, 40):
+        r = oracle.adam_solve(Q, g0[0], b0[0], evals=k, lr=lr, b1=b1, b2=b2, eps=eps, shots=16,
+                              seed=1)
+        got = np.concatenate([r["gamma"], r["beta"]])
+        assert np.max(np.abs(got - traj[k - 1])) <= 1e-12, k
