@@ -47,9 +47,9 @@ def folded_abs_sum(Q):
     return float(np.sum(np.abs(W)))
 
 
-# whole-state launch (n <= 12), single-tile and LDS-tile passes (13), register
-# tiles over one and two qubit sets (14..24) and three sets with lead-only
-# passes (25, 26), both precisions, p = 1 and 3
+# whole-state launch (complex64 n <= 14, complex128 n <= 13), register tiles
+# over one and two qubit sets (14..24) and three sets with lead-only passes
+# (25, 26), both precisions, p = 1 and 3
 CASES = [("c128", 5, 1), ("c128", 12, 3), ("c128", 13, 1), ("c128", 16, 3),
          ("c128", 20, 1), ("c128", 24, 3), ("c128", 25, 3), ("c64", 9, 3), ("c64", 14, 1),
          ("c64", 18, 3), ("c64", 22, 1), ("c64", 24, 3), ("c64", 26, 3)]

@@ -39,8 +39,9 @@ def cmax(Q):
     return float(np.max(np.abs(oracle.cost_table(Q))))
 
 
-# n <= 12: the whole-state adjoint, one case per register-bit count (n = 1..8
-# none, 9..12 one to four) and partial waves (n < 6)
+# the whole-state adjoint (n <= 12, complex64 n <= 13): one case per
+# register-bit count (n = 1..8 none, 9..13 one to five) and partial waves
+# (n < 6)
 GRAD_CASES = [("c128", 1, 2), ("c128", 3, 1), ("c128", 7, 2), ("c128", 8, 3), ("c128", 9, 2),
               ("c128", 10, 3), ("c128", 11, 2), ("c128", 12, 2), ("c128", 13, 2),
               ("c128", 14, 1), ("c128", 16, 3), ("c128", 17, 4), ("c128", 18, 2),
@@ -88,12 +89,13 @@ def test_grad_large_n_checkpointed(api, n, p):
         assert abs(e[0] - eo[0]) <= etol, (prec, e[0], eo[0])
 
 
-@pytest.mark.parametrize("prec,n", [("c64", 14), ("c128", 13), ("c64", 12), ("c128", 10)])
+@pytest.mark.parametrize("prec,n", [("c64", 14), ("c128", 13), ("c64", 12), ("c128", 10),
+                                    ("c64", 13)])
 def test_grad_at_max_layers(api, prec, n):
     """QAOA_MAX_P = 64 layers: on register tiles p + 1 = 65 passes on two
     qubit sets, whose checkpoint and adjoint tables make 2p + 1 = 129 jobs of
-    one tables launch; on the whole-state adjoint (n <= 12) 64 layers undone
-    in registers."""
+    one tables launch; on the whole-state adjoint (n <= 12, complex64 13) 64
+    layers undone in registers."""
     p = 64
     Q = workloads.qubos(1, n, 3300 + n)
     g, b = workloads.params(1, p, 3400 + n, lead=(1,))
