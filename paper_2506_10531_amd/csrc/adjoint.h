@@ -215,7 +215,7 @@ bwd_kernel(BwdArgs A) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n = d.n, nlog = n - K;
   // runs under 128 bytes: the two tiles sharing each line run on one XCD
-  const uint64_t tile = xcd_tile<KIND == 2 && (1u << G::C) * sizeof(V) < 128>();
+  const uint64_t tile = xcd_tile<(KIND == 2 && (1u << G::C) * sizeof(V) < 128) ? 2 : 1>();
   const uint64_t st = tile >> nlog, ti = tile & ((1ull << nlog) - 1ull);
   const uint64_t zb = tile_base<K, G::C>(ti, KIND, d.a);
   double* const Wsh = reinterpret_cast<double*>(buf);

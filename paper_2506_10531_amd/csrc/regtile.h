@@ -838,15 +838,41 @@ inline int pass_shape(const PassDesc& d, int p) {
 }
 
 // Tile index of this work-group.  Work-groups are dealt to the 8 XCDs (each
-// with its own L2) in turn.  When a tile's contiguous runs are shorter than a
-// 128 B line, tiles t and t ^ 1 share every line; PAIR maps them to the
-// work-groups 8 apart, i.e. to one XCD back to back, so one L2 sees both
-// halves of each line.  A bijection of [0, gridDim.x) for grids of 16k.
-template <bool PAIR>
+// with its own L2) in turn.  GRP > 1 maps GRP consecutive tiles, whose runs
+// lie next to each other in memory, to work-groups 8 apart, i.e. to one XCD
+// back to back: when a tile's runs are shorter than a 128 B line, tiles t and
+// t ^ 1 share every line, and with runs of a line or less one XCD then fetches
+// and writes GRP adjacent runs as one stretch.  A bijection of [0, gridDim.x)
+// when gridDim.x is a multiple of 8 GRP (otherwise the identity).
+template <int GRP>
+__host__ __device__ __forceinline__ uint32_t xcd_map(uint32_t b, uint32_t grid) {
+  if constexpr (GRP == 1) {
+    (void)grid;
+    return b;
+  } else {
+    constexpr uint32_t span = 8u * GRP;
+    constexpr int lg = GRP == 2 ? 1 : (GRP == 4 ? 2 : 3);
+    static_assert(GRP == 2 || GRP == 4 || GRP == 8, "GRP");
+    if (grid % span) return b;
+    return (b & ~(span - 1u)) | ((b & 7u) << lg) | ((b >> 3) & (GRP - 1u));
+  }
+}
+template <int GRP>
 __device__ __forceinline__ uint64_t xcd_tile() {
-  const uint32_t b = blockIdx.x;
-  if (!PAIR || (gridDim.x & 15u)) return b;
-  return (b & ~15u) | ((b & 7u) << 1) | ((b >> 3) & 1u);
+  return xcd_map<GRP>(blockIdx.x, gridDim.x);
+}
+
+// Tiles per XCD group for a pass shape on runs of RUN bytes (kernel traces,
+// n = 24, 16 states): complex64 128 B runs, first 0.495 / 0.511 / 0.500 ms
+// with groups of 2 / 4 / 8, middle 0.995 / 0.923 / 0.943, last 0.508 / 0.503
+// / 0.493; complex128 64 B runs, first 1.484 / 1.387 / 1.456, middle 2.676 /
+// 2.573 / 2.334, last 1.218 / 1.203 / 1.074.  Longer runs keep the plain
+// order.
+template <int KIND, int RUN, int PT>
+constexpr int tile_group() {
+  if (KIND != 2 || RUN > 128) return 1;
+  if (RUN == 128) return PT == P_FIRST ? 2 : (PT == P_LAST ? 8 : 4);
+  return PT == P_FIRST ? 4 : 8;
 }
 
 // One tile of one pass per work-group (tile index = state * 2^(n-K) + tile
@@ -874,7 +900,7 @@ fwd_kernel(FwdArgs A) {
   const PassDesc& d = A.d;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n = d.n, nlog = n - K;
-  const uint64_t tile = xcd_tile<KIND == 2 && (1u << G::C) * sizeof(V) < 128>();
+  const uint64_t tile = xcd_tile<tile_group<KIND, (1 << G::C) * (int)sizeof(V), PT>()>();
   const uint64_t st = tile >> nlog, ti = tile & ((1ull << nlog) - 1ull);
   const uint64_t zb = tile_base<K, G::C>(ti, KIND, d.a);
   const V* const gin = reinterpret_cast<const V*>(A.in) + st * A.stride + zb;

@@ -2,7 +2,7 @@
 // the host (test infrastructure: built and run by tests/test_index_maps_cpu.py;
 // it launches nothing).  It calls the same __host__ __device__ helpers the
 // kernels use for their addresses (thread_bits, reg_off, pair_base, pair_rel,
-// tile_base, transpose_bases, phys) and checks, for every geometry and every
+// tile_base, transpose_bases, phys, xcd_map) and checks, for every geometry and every
 // pass the library plans for n up to 34:
 //   * every layout places each tile bit in exactly one register, lane or wave
 //     slot, with tile bit 0 in register slot 0;
@@ -15,7 +15,8 @@
 //     reads back into every register the amplitude that the target layout
 //     assigns to it (tile index l ^ M when relabelling);
 //   * the rounds of every half-mixer, in its lead and its trail order, mix
-//     each tile bit of the pass's range [MIXLO, K) exactly once and no other.
+//     each tile bit of the pass's range [MIXLO, K) exactly once and no other;
+//   * the work-group -> tile order (xcd_map) is a bijection of the grid.
 // Prints "ok <checks>" and exits 0, or prints the first failures and exits 1.
 #include "../paper_2506_10531_amd/csrc/geom12.h"
 #include "../paper_2506_10531_amd/csrc/geom13.h"
@@ -270,6 +271,37 @@ void g12d_kind2(std::integer_sequence<int, Ms...>) {
   (transposes_set0_seq<G12D, Ms + 2>(), ...);
 }
 
+// The work-group -> tile order of the passes: a bijection of [0, grid) for
+// every grid, and on grids that are a multiple of 8 GRP each XCD (work-group
+// index mod 8) runs GRP consecutive tiles back to back.
+template <int GRP>
+void check_xcd_map() {
+  for (uint32_t grid : {1u, 7u, 8u, 16u, 24u, 32u, 40u, 64u, 96u, 128u, 200u, 1024u, 4096u, 65536u}) {
+    std::vector<int> seen(grid, 0);
+    bool inside = true;
+    for (uint32_t b = 0; b < grid; ++b) {
+      const uint32_t t = xcd_map<GRP>(b, grid);
+      if (t >= grid) inside = false;
+      else ++seen[t];
+    }
+    check(inside, "xcd_map stays inside the grid", "xcd", GRP, grid);
+    check(std::all_of(seen.begin(), seen.end(), [](int c) { return c == 1; }),
+          "xcd_map is a bijection", "xcd", GRP, grid);
+    if (grid % (8u * GRP)) {
+      bool id = true;
+      for (uint32_t b = 0; b < grid; ++b) id = id && xcd_map<GRP>(b, grid) == b;
+      check(id, "xcd_map is the identity on other grids", "xcd", GRP, grid);
+      continue;
+    }
+    bool grouped = true;
+    for (uint32_t b = 0; b < grid; b += 8u * GRP)
+      for (uint32_t x = 0; x < 8; ++x)
+        for (uint32_t j = 0; j < (uint32_t)GRP; ++j)
+          grouped = grouped && xcd_map<GRP>(b + 8u * j + x, grid) == b + GRP * x + j;
+    check(grouped, "xcd_map deals GRP consecutive tiles to one XCD", "xcd", GRP, grid);
+  }
+}
+
 template <class G, int... Ls>
 void layouts(const char* g, std::integer_sequence<int, Ls...>) {
   (check_layout<G, Ls>(g), ...);
@@ -278,6 +310,11 @@ void layouts(const char* g, std::integer_sequence<int, Ls...>) {
 }  // namespace
 
 int main() {
+  // work-group -> tile order
+  check_xcd_map<1>();
+  check_xcd_map<2>();
+  check_xcd_map<4>();
+  check_xcd_map<8>();
   // layouts
   layouts<G14T<4>>("G14T", std::make_integer_sequence<int, 5>());
   layouts<G13D>("G13T", std::make_integer_sequence<int, 6>());
