@@ -850,9 +850,9 @@ __host__ __device__ __forceinline__ uint32_t xcd_map(uint32_t b, uint32_t grid) 
     (void)grid;
     return b;
   } else {
+    static_assert(GRP > 1 && GRP <= 64 && (GRP & (GRP - 1)) == 0, "GRP");
     constexpr uint32_t span = 8u * GRP;
-    constexpr int lg = GRP == 2 ? 1 : (GRP == 4 ? 2 : 3);
-    static_assert(GRP == 2 || GRP == 4 || GRP == 8, "GRP");
+    constexpr int lg = GRP == 2 ? 1 : GRP == 4 ? 2 : GRP == 8 ? 3 : GRP == 16 ? 4 : GRP == 32 ? 5 : 6;
     if (grid % span) return b;
     return (b & ~(span - 1u)) | ((b & 7u) << lg) | ((b >> 3) & (GRP - 1u));
   }
@@ -865,14 +865,15 @@ __device__ __forceinline__ uint64_t xcd_tile() {
 // Tiles per XCD group for a pass shape on runs of RUN bytes (kernel traces,
 // n = 24, 16 states): complex64 128 B runs, first 0.495 / 0.511 / 0.500 ms
 // with groups of 2 / 4 / 8, middle 0.995 / 0.923 / 0.943, last 0.508 / 0.503
-// / 0.493; complex128 64 B runs, first 1.484 / 1.387 / 1.456, middle 2.676 /
-// 2.573 / 2.334, last 1.218 / 1.203 / 1.074.  Longer runs keep the plain
-// order.
+// / 0.493 (0.496 with 16); complex128 64 B runs, first 1.484 / 1.387 / 1.456,
+// middle 2.676 / 2.573 / 2.334 and then 2.253 / 2.283 with 16 / 32, last
+// 1.218 / 1.203 / 1.074 and then 1.030 / 1.030.  Longer runs keep the plain
+// order (groups of 2-8 on 256 B runs slowed the n = 32 step by 1-2%).
 template <int KIND, int RUN, int PT>
 constexpr int tile_group() {
   if (KIND != 2 || RUN > 128) return 1;
   if (RUN == 128) return PT == P_FIRST ? 2 : (PT == P_LAST ? 8 : 4);
-  return PT == P_FIRST ? 4 : 8;
+  return PT == P_FIRST ? 4 : 16;
 }
 
 // One tile of one pass per work-group (tile index = state * 2^(n-K) + tile

@@ -315,6 +315,8 @@ int main() {
   check_xcd_map<2>();
   check_xcd_map<4>();
   check_xcd_map<8>();
+  check_xcd_map<16>();
+  check_xcd_map<32>();
   // layouts
   layouts<G14T<4>>("G14T", std::make_integer_sequence<int, 5>());
   layouts<G13D>("G13T", std::make_integer_sequence<int, 6>());
