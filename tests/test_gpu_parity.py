@@ -111,6 +111,16 @@ def test_multiset_c128_state(api, n, p):
     run_case(api, n, p, S=1, prec="c128")
 
 
+@pytest.mark.parametrize("B,S", [(4, 2), (3, 1)])
+def test_xcd_grouped_tile_order(api, B, S):
+    """complex128 passes on 64-byte runs deal 4 (first pass) or 16 (middle and
+    last passes) consecutive tiles to one XCD when the grid, states x 2^(n-13)
+    tiles, is a multiple of 8 x that group, and keep the launch order
+    otherwise.  At n = 18 (32 tiles per state) 8 states take the grouped
+    order in every pass; 3 states (96 tiles) take it in the first pass only."""
+    run_case(api, 18, 3, S=S, prec="c128", B=B, seed=11)
+
+
 def test_plain_n10_all_sets_with_probabilities(api):
     """64 parameter sets, p = 2, complex128, <C> and probabilities."""
     W = workloads.WORKLOADS["plain_n10"]
