@@ -556,8 +556,21 @@ __device__ __forceinline__ void store_tile(const typename G::V (&v)[Dim<G>::NA],
                                            typename G::V* base, int lane, int wave, int kind,
                                            int a, bool sw) {
   const uint64_t tb = pair_base<G, L>(lane, wave, kind, a);
-  if (sw) store_rows<G, L, true>(v, base, tb, kind, a);
-  else store_rows<G, L, false>(v, base, tb, kind, a);
+  if constexpr (sizeof(typename G::V) == 16) {
+    // complex128: an amplitude per 16-byte store, so the flipped order is an
+    // address offset (kept out of a branch, whose two store sequences the
+    // compiler may merge through private memory)
+    const uint64_t s0 = sw ? 1u : 0u;
+#pragma unroll
+    for (int q = 0; q < Dim<G>::NP; ++q) {
+      const uint64_t o = tb + pair_rel<G, L>(q, kind, a);
+      base[o + s0] = v[q << 1];
+      base[o + (s0 ^ 1u)] = v[(q << 1) | 1];
+    }
+  } else {
+    if (sw) store_rows<G, L, true>(v, base, tb, kind, a);
+    else store_rows<G, L, false>(v, base, tb, kind, a);
+  }
 }
 
 // |psi|^2 * scale in the state precision (float for complex64, double for
